@@ -1,0 +1,121 @@
+"""Seeded synthetic workloads: jittered square lattices, Gaussian-vortex data.
+
+This module only draws inputs.  It holds none of the interpolation method's
+arithmetic, so both the GPU path and the CPU oracle can be fed from it.
+
+The point sets follow the paper's experiments (Section 3.1): points on a
+square lattice, optionally shifted by a random amount to make them
+quasi-scattered.  Here the lattice is cell-centred on [-1, 1]^2 with spacing
+h = 2 / n_side and every coordinate is shifted by an independent uniform
+offset in [-0.1 h, +0.1 h].  The Gaussian width is fixed through the overlap
+ratio h / sigma, the quantity the paper's convergence study varies
+(Section 3.2), and the matvec cutoff is r_c = 6 sigma.
+
+The interpolated data is a normalised Gaussian vortex
+f(x) = exp(-|x|^2 / r0^2) / (pi r0^2), the kind of field the paper's target
+application (vortex particle methods, Section 1) interpolates.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 5413
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n_side: int
+    h_over_sigma: float = 0.8
+    jitter: float = 0.1          # fraction of h, uniform +-jitter*h per coordinate
+    r0: float = 0.2              # Gaussian-vortex core radius of the data
+    rtol: float = 1e-10
+    seed: int = SEED_BASE
+    cutoff_sigmas: float = 6.0
+    overlap: int = 1
+    notes: str = field(default="", compare=False)
+
+    @property
+    def n(self) -> int:
+        return self.n_side * self.n_side
+
+    @property
+    def h(self) -> float:
+        return 2.0 / self.n_side
+
+    @property
+    def sigma(self) -> float:
+        return self.h / self.h_over_sigma
+
+    @property
+    def cutoff(self) -> float:
+        return self.cutoff_sigmas * self.sigma
+
+    def points(self) -> np.ndarray:
+        return jittered_lattice(self.n_side, self.jitter, self.seed)
+
+    def values(self, pts: np.ndarray | None = None) -> np.ndarray:
+        if pts is None:
+            pts = self.points()
+        return gaussian_vortex(pts, self.r0)
+
+
+def jittered_lattice(n_side: int, jitter: float = 0.1, seed: int = SEED_BASE,
+                     lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """n_side^2 points, row-major (index = iy * n_side + ix), shape (N, 2) float64.
+
+    Lattice x_k = lo + (k + 1/2) h with h = (hi - lo) / n_side, each coordinate
+    shifted by an independent U(-jitter*h, +jitter*h) drawn from PCG64(seed).
+    """
+    h = (hi - lo) / n_side
+    k = np.arange(n_side, dtype=np.float64)
+    c = lo + (k + 0.5) * h
+    xx, yy = np.meshgrid(c, c, indexing="xy")        # yy varies along rows
+    pts = np.stack([xx.ravel(), yy.ravel()], axis=1)
+    if jitter:
+        rng = np.random.default_rng(seed)
+        pts = pts + rng.uniform(-jitter * h, jitter * h, size=pts.shape)
+    return np.ascontiguousarray(pts, dtype=np.float64)
+
+
+def gaussian_vortex(pts: np.ndarray, r0: float = 0.2) -> np.ndarray:
+    """f(x) = exp(-|x|^2 / r0^2) / (pi r0^2), unit total circulation."""
+    r2 = pts[:, 0] ** 2 + pts[:, 1] ** 2
+    return np.exp(-r2 / (r0 * r0)) / (np.pi * r0 * r0)
+
+
+def random_weights(n: int, seed: int) -> np.ndarray:
+    """w ~ U(-1, 1), float64, for matvec micro-benchmarks and parity tests."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n)
+
+
+def staggered_lattice(n_side: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Evaluation points midway between lattice nodes: (n_side - 1)^2 points."""
+    h = (hi - lo) / n_side
+    c = lo + (np.arange(n_side - 1, dtype=np.float64) + 1.0) * h
+    xx, yy = np.meshgrid(c, c, indexing="xy")
+    return np.ascontiguousarray(np.stack([xx.ravel(), yy.ravel()], axis=1))
+
+
+# The workloads, sized like the paper's lattice runs (Sections 3 and 4).
+MINI = Workload("mini", 44, 0.8, rtol=1e-10, seed=SEED_BASE + 100,
+                notes="44x44 lattice, N=1936: small enough for dense checks")
+C0 = Workload("c0", 100, 0.8, rtol=1e-10, seed=SEED_BASE + 0,
+              notes="N=10,000, h=0.02, GMRES(30) to 1e-10")
+C1 = Workload("c1", 1000, 0.8, rtol=1e-12, seed=SEED_BASE + 1,
+              notes="N=1,000,000, h=0.002, GMRES(30) to 1e-12")
+C2 = {r: Workload(f"c2_{r}", 2048, r, rtol=1e-12, seed=SEED_BASE + 2,
+                  notes="N=4,194,304 mixed-precision sweep")
+      for r in (0.6, 0.8, 1.0)}
+C4 = Workload("c4", 7072, 0.8, rtol=1e-14, seed=SEED_BASE + 4,
+              notes="N=50,013,184, largest single problem")
+
+WORKLOADS = {w.name: w for w in (MINI, C0, C1, C4, *C2.values())}
+
+
+def sub_lattice(w: Workload, n_side: int) -> Workload:
+    """A smaller lattice with the same spacing ratio, jitter and cutoff rule."""
+    return Workload(f"{w.name}_sub{n_side}", n_side, w.h_over_sigma, w.jitter, w.r0,
+                    w.rtol, w.seed, w.cutoff_sigmas, w.overlap)

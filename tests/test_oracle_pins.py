@@ -1,0 +1,289 @@
+"""Pins of the CPU oracle against the paper and the mathematics (no GPU).
+
+Every check here compares the oracle with something other than itself:
+brute-force O(N^2) sums, dense LU / explicit-inverse solves, closed forms of
+the lattice Gaussian sum (Poisson summation), number-theoretic lattice-point
+counts, and invariants (symmetry, positive definiteness, unit circulation).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_0909_5413_amd import workloads as W
+from tests import bruteforce as bf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def lattice(n_side, ratio, jitter=0.1, seed=1):
+    w = W.Workload("t", n_side, ratio, jitter=jitter, seed=seed)
+    return w, w.points()
+
+
+# --------------------------------------------------------------------- binning
+@pytest.mark.parametrize("n_side,ratio", [(44, 0.8), (100, 0.8), (37, 0.6)])
+def test_binning_invariants(oracle_mod, n_side, ratio):
+    w, pts = lattice(n_side, ratio)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    cell_of, perm, cs = P.binning()
+    n = pts.shape[0]
+    assert sorted(perm.tolist()) == list(range(n))                     # a permutation
+    assert cs[0] == 0 and cs[-1] == n and np.all(np.diff(cs) >= 0)    # monotone offsets
+    assert np.array_equal(np.diff(cs), np.bincount(cell_of, minlength=P.ncells))
+    # lexicographic on (cell, original index)
+    key = cell_of[perm].astype(np.int64) * n + perm
+    assert np.all(np.diff(key) > 0)
+    # every point lies in its cell's box [x0 + cx L, x0 + (cx+1) L) up to rounding
+    cx, cy = cell_of % P.ncx, cell_of // P.ncx
+    slack = 4e-16 * (1.0 + np.abs(pts).max())
+    lo_x, lo_y = P.x0 + cx * P.L, P.y0 + cy * P.L
+    assert np.all(pts[:, 0] >= lo_x - slack) and np.all(pts[:, 1] >= lo_y - slack)
+    assert np.all(pts[:, 0] < lo_x + P.L + slack) and np.all(pts[:, 1] < lo_y + P.L + slack)
+    assert P.x0 == pts[:, 0].min() and P.y0 == pts[:, 1].min() and P.L == w.cutoff
+
+
+# --------------------------------------------------------------- neighbour counts
+def test_neighbour_counts_bruteforce(oracle_mod):
+    w, pts = lattice(44, 0.8)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    _, nnb = P.matvec(np.ones(w.n), with_counts=True)
+    mask = bf.cutoff_mask(pts[:, 0], pts[:, 1], pts[:, 0], pts[:, 1], w.cutoff)
+    assert np.array_equal(nnb, mask.sum(axis=1))
+
+
+def read_circle_counts():
+    rows = []
+    with open(os.path.join(GOLDEN, "gauss_circle_counts.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                r, c, on = line.split()
+                rows.append((float(r), int(c), int(on)))
+    return rows
+
+
+@pytest.mark.parametrize("r_over_h,count,on_circle", read_circle_counts())
+def test_interior_counts_equal_gauss_circle(oracle_mod, r_over_h, count, on_circle):
+    ratio = 6.0 / r_over_h                      # r_c = 6 sigma, sigma = h / ratio
+    n_side = 48
+    w, pts = lattice(n_side, ratio, jitter=0.0)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    _, nnb = P.matvec(np.ones(w.n), with_counts=True)
+    margin = w.cutoff + 1e-12
+    inner = np.all((pts > -1 + margin) & (pts < 1 - margin), axis=1)
+    assert inner.sum() > 50
+    got = nnb[inner]
+    if on_circle == 0:
+        assert np.all(got == count)
+    else:   # points exactly on the circle: floating point decides each of them
+        assert np.all((got >= count - on_circle) & (got <= count))
+
+
+# ----------------------------------------------------------------------- matvec
+def test_matvec_matches_bruteforce(oracle_mod):
+    w, pts = lattice(44, 0.8)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    v = W.random_weights(w.n, 7)
+    y = P.matvec(v)
+    A = bf.dense_matrix(pts, w.sigma, w.cutoff)
+    ref = A @ v
+    scale = np.abs(A) @ np.abs(v)
+    assert np.all(np.abs(y - ref) <= 1e-14 * scale)
+
+
+def test_matvec_truncation_tail_bound(oracle_mod):
+    w, pts = lattice(44, 0.8)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    v = W.random_weights(w.n, 8)
+    y = P.matvec(v)
+    full = bf.dense_matrix(pts, w.sigma, None) @ v
+    far = ~bf.cutoff_mask(pts[:, 0], pts[:, 1], pts[:, 0], pts[:, 1], w.cutoff)
+    phi_rc = bf.gaussian(w.cutoff ** 2, w.sigma)
+    bound = phi_rc * (far * np.abs(v)[None, :]).sum(axis=1)
+    assert np.all(np.abs(full - y) <= bound * (1 + 1e-12) + 1e-13 * np.abs(full).max())
+    # and the tail is not empty: the truncation really drops terms
+    assert np.abs(full - y).max() > 0
+
+
+@pytest.mark.parametrize("ratio", [0.8, 1.0, 0.6])
+def test_matvec_lattice_closed_form(oracle_mod, ratio):
+    """w = 1 on an unjittered lattice: interior y equals the finite lattice sum
+    S = (2 pi sigma^2)^-1 sum_{k in Z^2, |k| h <= r_c} exp(-h^2 |k|^2 / (2 sigma^2)),
+    and by Poisson summation S h^2 = 1 up to the Gaussian mass beyond r_c,
+    exp(-r_c^2 / (2 sigma^2)) = e^-18 (aliasing terms are below e^-30 here)."""
+    n_side = 48
+    w, pts = lattice(n_side, ratio, jitter=0.0)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    y = P.matvec(np.ones(w.n))
+    h, s = w.h, w.sigma
+    kmax = int(np.ceil(w.cutoff / h)) + 1
+    a = np.arange(-kmax, kmax + 1)
+    A, B = np.meshgrid(a, a)
+    q = (A * A + B * B).astype(np.float64)
+    inside = q * h * h <= w.cutoff ** 2 * (1 - 1e-12)   # strictly inside: on-circle points excluded
+    S = np.exp(-h * h * q[inside] / (2 * s * s)).sum() / (2 * np.pi * s * s)
+    on = np.abs(q * h * h - w.cutoff ** 2) <= 1e-12 * w.cutoff ** 2
+    S_on = np.exp(-h * h * q[on] / (2 * s * s)).sum() / (2 * np.pi * s * s)
+    margin = w.cutoff + 1e-12
+    inner = np.all((pts > -1 + margin) & (pts < 1 - margin), axis=1)
+    yi = y[inner]
+    # each on-circle lattice point may fall either side of the cutoff
+    assert np.all((yi >= S * (1 - 1e-13)) & (yi <= (S + S_on) * (1 + 1e-13)))
+    tail = np.exp(-w.cutoff ** 2 / (2 * s * s))
+    # the lattice tail beyond r_c is a Riemann sum of the continuous tail e^-18
+    assert abs(S * h * h - 1) < 2 * tail and abs((S + S_on) * h * h - 1) < 2 * tail
+
+
+def test_symmetric_and_positive_definite(oracle_mod):
+    w, pts = lattice(16, 0.8, jitter=0.0)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    A = np.stack([P.matvec(e) for e in np.eye(w.n)], axis=1)
+    assert np.array_equal(A, A.T)                           # bit-symmetric
+    ev = np.linalg.eigvalsh(A) * w.h ** 2
+    # lattice symbol bounds: min ~ 4 exp(-pi^2 sigma^2/h^2) - e^-18, max <= 1
+    s = w.sigma / w.h
+    lo = 4 * np.exp(-np.pi ** 2 * s * s) - np.exp(-18.0)
+    assert ev.min() >= lo * (1 - 1e-6) and ev.max() <= 1 + 1e-9
+    # the untruncated Gaussian is positive definite (Micchelli)
+    np.linalg.cholesky(bf.dense_matrix(pts, w.sigma, None))
+
+
+# ------------------------------------------------------------------------- RASM
+def test_cholesky_of_local_blocks(oracle_mod):
+    w, pts = lattice(44, 0.8)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    P.rasm_setup()
+    u = np.finfo(float).eps / 2
+    for cell in (0, 7, P.ncx + 1, P.ncells // 2, P.ncells - 1):
+        mem, kc, L = P.rasm_block(cell)
+        sub = pts[mem]
+        A = bf.dense_matrix(sub, w.sigma, None)
+        assert np.allclose(L, np.tril(L))
+        n = len(mem)
+        err = np.linalg.norm(L @ L.T - A) / np.linalg.norm(A)
+        assert err <= 10 * n * u
+        # centre cell last, neighbours first
+        cx, cy, _, _ = bf.cells_of(pts, w.cutoff)
+        c_x, c_y = cell % P.ncx, cell // P.ncx
+        own = set(np.nonzero((cx == c_x) & (cy == c_y))[0].tolist())
+        assert set(mem[n - kc:].tolist()) == own
+        blk = set(np.nonzero((abs(cx - c_x) <= 1) & (abs(cy - c_y) <= 1))[0].tolist())
+        assert set(mem.tolist()) == blk
+
+
+@pytest.mark.parametrize("overlap", [1, 0, 2])
+def test_rasm_matches_explicit_inverse(oracle_mod, overlap):
+    w, pts = lattice(30, 0.8)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff, overlap)
+    P.rasm_setup()
+    v = W.random_weights(w.n, 3)
+    z = P.rasm_apply(v)
+    ref = bf.rasm_dense(pts, w.sigma, w.cutoff, overlap) @ v
+    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+# ------------------------------------------------------------------------ GMRES
+def test_gmres_matches_dense_solve(oracle_mod):
+    w, pts = lattice(44, 0.8)
+    f = w.values(pts)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    x, info = P.gmres(f, 30, 1e-12)
+    assert info.status == 0
+    A = bf.dense_matrix(pts, w.sigma, w.cutoff)
+    res = np.linalg.norm(f - A @ x) / np.linalg.norm(f)
+    assert res <= 1.5e-12
+    xd = np.linalg.solve(A, f)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(x - xd) <= kappa * 3e-12 * np.linalg.norm(xd)
+    assert abs(info.rel_residual - res) <= 1e-13
+
+
+def test_gmres_single_subdomain_is_direct(oracle_mod):
+    """Cutoff larger than the point set: one cell, truncation drops nothing and
+    the preconditioner is the exact inverse, so one Arnoldi step solves it."""
+    w, pts = lattice(12, 1.5)
+    f = w.values(pts)
+    big = 10.0
+    P = oracle_mod.Problem(pts, w.sigma, big)
+    assert P.ncells == 1
+    x, info = P.gmres(f, 30, 1e-11)
+    assert info.status == 0 and info.iterations == 1
+    xd = np.linalg.solve(bf.dense_matrix(pts, w.sigma, None), f)
+    assert np.linalg.norm(x - xd) <= 1e-11 * np.linalg.norm(xd)
+
+
+def test_gmres_nearly_diagonal(oracle_mod):
+    """h/sigma = 3: off-diagonal entries are e^-4.5 of the diagonal or less, so
+    lambda is close to 2 pi sigma^2 f and very few iterations are needed."""
+    w, pts = lattice(30, 3.0)
+    f = w.values(pts)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    x, info = P.gmres(f, 30, 1e-10)
+    assert info.status == 0 and info.iterations <= 5
+    approx = 2 * np.pi * w.sigma ** 2 * f
+    assert np.linalg.norm(x - approx) <= 0.2 * np.linalg.norm(approx)
+
+
+def test_iterations_independent_of_n(oracle_mod):
+    """Section 3.2: at fixed h/sigma and subdomain size the iteration count does
+    not change with N."""
+    its = []
+    for n_side in (44, 70, 100):
+        w = W.Workload("t", n_side, 0.8, seed=11)
+        pts = w.points()
+        P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+        _, info = P.gmres(w.values(pts), 30, 1e-10)
+        assert info.status == 0
+        its.append(info.iterations)
+    assert max(its) - min(its) <= 2, its
+
+
+def test_iterations_grow_with_sigma_over_h(oracle_mod):
+    """Section 3.1: the larger sigma/h, the worse conditioned and slower."""
+    its = []
+    for ratio in (1.0, 0.9, 0.8):
+        w = W.Workload("t", 60, ratio, seed=12)
+        pts = w.points()
+        P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+        _, info = P.gmres(w.values(pts), 30, 1e-12)
+        assert info.status == 0
+        its.append(info.iterations)
+    assert its[0] <= its[1] <= its[2], its
+
+
+def test_data_reproduced_and_vortex_interpolated(oracle_mod):
+    w = W.C0
+    pts = w.points()
+    f = w.values(pts)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    x, info = P.gmres(f, 30, w.rtol)
+    assert info.status == 0
+    s_nodes = P.evaluate(x, pts)
+    assert np.linalg.norm(s_nodes - f) <= 1.01 * w.rtol * np.linalg.norm(f)
+    # unit circulation: sum of weights = integral of the interpolant = integral of f
+    assert abs(x.sum() - 1.0) < 1e-4
+    # interpolant between the nodes approaches the closed-form vortex
+    stag = W.staggered_lattice(w.n_side)
+    err = np.abs(P.evaluate(x, stag) - W.gaussian_vortex(stag, w.r0)).max() / f.max()
+    assert err < 2e-2, err
+
+
+# ----------------------------------------------------------------------- errors
+def test_error_codes(oracle_mod):
+    w, pts = lattice(20, 0.8)
+    bad = pts.copy()
+    bad[5] = bad[9]
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.Problem(bad, w.sigma, w.cutoff)
+    assert e.value.code == 2
+    bad = pts.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.Problem(bad, w.sigma, w.cutoff)
+    assert e.value.code == 1
+    for sig, cut, ov in ((0.0, 0.1, 1), (0.1, -1.0, 1), (0.1, 0.1, -1), (np.inf, 0.1, 1)):
+        with pytest.raises(oracle_mod.OracleError):
+            oracle_mod.Problem(pts, sig, cut, ov)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    _, info = P.gmres(w.values(pts), 30, 1e-30, max_iters=5, raise_on_error=False)
+    assert info.status == 6 and info.iterations == 5
