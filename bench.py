@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Whole-job throughput of the Gaussian-RBF interpolation hot path on one MI355X.
+
+One step = the whole hot path on the resident N = 1,000,000 workload (jittered
+1000 x 1000 lattice on [-1, 1]^2, h/sigma = 0.8, cutoff 6 sigma, 3x3-cell RASM
+subdomains, GMRES(30) to a relative residual of 1e-12): cell binning, local
+Cholesky factorisations and inverse rows, and the preconditioned GMRES solve,
+all through the C ABI on device buffers.
+
+value = in-cutoff Gaussian interactions evaluated by the FP64 matvecs of the
+timed steps / timed seconds (the metric's unit, whole job).  The JSON line also
+carries the seconds to 1e-12 in FP64 and mixed precision, per-kernel rooflines
+(HIP events on the library's stream) and the CPU oracle timed on a bounded
+sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gaussian matvec interactions/s; s to 1e-12 residual, FP64 vs mixed; p99 lat"
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector (= FP64 matrix)
+VALU_OPS_PER_S = 256 * 64 * 2.4e9   # one FP64 VALU lane-op per lane per clock
+OPS_PER_INTERACTION = 20       # FP64 VALU ops charged per in-cutoff interaction
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def block_sizes(cell_start, ncx, ncy, overlap=1):
+    """n_omega and n_c per cell from the binning (host arithmetic on counts)."""
+    import numpy as np
+    cnt = np.diff(cell_start.astype(np.int64)).reshape(ncy, ncx)
+    pad = np.pad(cnt, overlap)
+    k = 2 * overlap + 1
+    tot = np.zeros_like(cnt)
+    for dy in range(k):
+        for dx in range(k):
+            tot += pad[dy:dy + ncy, dx:dx + ncx]
+    return tot.ravel(), cnt.ravel()
+
+
+def event_time(torch, stream, fn, reps):
+    """Average milliseconds of fn() over reps launches, HIP events on stream."""
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def cpu_baseline(workload, n_side):
+    import numpy as np
+    import oracle
+    from paper_0909_5413_amd import workloads as W
+    w = W.sub_lattice(workload, n_side)
+    pts = w.points()
+    f = w.values(pts)
+    P = oracle.Problem(pts, w.sigma, w.cutoff, w.overlap)
+    _, nnb = P.matvec(np.ones(w.n), with_counts=True)
+    inter = int(nnb.sum())
+    P.close()
+    t0 = time.perf_counter()
+    P = oracle.Problem(pts, w.sigma, w.cutoff, w.overlap)
+    P.rasm_setup()
+    x, info = P.gmres(f, 30, workload.rtol)
+    dt = time.perf_counter() - t0
+    matvecs = info.iterations + len(info.history)
+    return {
+        "value": inter * matvecs / dt, "unit": "interactions/s",
+        "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": (f"oracle setup + FP64 GMRES(30) solve to {workload.rtol:g} on a "
+                   f"{n_side}x{n_side} jittered lattice (N={w.n}) with the same h/sigma, cutoff "
+                   f"and subdomain rule: {matvecs} matvecs x {inter} interactions in {dt:.2f} s"),
+        "seconds": dt, "iterations": info.iterations,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--cpu-side", type=int, default=300, help="oracle sample lattice side")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding of this path is a design, not a run", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0909_5413_amd as R
+    from paper_0909_5413_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    R.lib()
+    w = W.WORKLOADS[args.workload]
+    log("workload", w.name, "N", w.n)
+    pts = w.points()
+    f = w.values(pts)
+    dev = torch.device("cuda:0")
+    d_pts = torch.tensor(pts, device=dev)
+    d_f = torch.tensor(f, device=dev)
+    d_lam = torch.empty(w.n, device=dev, dtype=torch.float64)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    # interactions per matvec: a property of the point set (counted once)
+    h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+    _, inter = R.rbf_neighbor_counts(h, w.n)
+    _, (ncx, ncy) = R.rbf_grid(h)
+    _, _, cs = R.rbf_binning(h, w.n)
+    R.rbf_destroy(h)
+    n_omega, n_c = block_sizes(cs, ncx, ncy, w.overlap)
+    log("interactions/matvec", inter, "cells", ncx * ncy)
+
+    opts = R.default_opts(rtol=w.rtol, stream=stream)
+
+    def step():
+        h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+        try:
+            R.rbf_precond_setup(h, R.RBF_FP64, stream)
+            info, _ = R.rbf_solve_device(h, d_lam, opts)
+        finally:
+            R.rbf_destroy(h)
+        return info.as_dict()
+
+    for i in range(args.warmup):
+        info = step()
+        log("warmup", i, "iterations", info["iterations"], "rel", info["rel_residual"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        infos.append(step())
+        log("step", i, "done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mv = sum(i["matvecs64"] for i in infos)
+    value = inter * mv / dt
+    ms_step = 1e3 * dt / args.steps
+    last = infos[-1]
+    log("ms/step", ms_step, "value", value)
+
+    # ---- per-kernel rooflines: HIP events on the stream the library uses -------
+    h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+    kernels = {}
+    try:
+        t_pc = event_time(torch, stream, lambda: R.rbf_precond_setup(h, R.RBF_FP64, stream), 1)
+        own = n_c > 0
+        no, nc = n_omega[own].astype(np.float64), n_c[own].astype(np.float64)
+        flops = float(np.sum(no ** 3 / 3.0 + nc * no ** 2))
+        kernels["precond_setup64"] = {
+            "bound": "alu", "achieved": flops / (t_pc * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "ms": t_pc, "flops_per_launch": flops}
+        wv = torch.tensor(W.random_weights(w.n, W.SEED_BASE + 11), device=dev)
+        yv = torch.empty_like(wv)
+        R.rbf_matvec_device(h, wv, yv, R.RBF_FP64, R.RBF_ORDER_SORTED, stream)
+        t_mv = event_time(torch, stream, lambda: R.rbf_matvec_device(
+            h, wv, yv, R.RBF_FP64, R.RBF_ORDER_SORTED, stream), args.kernel_reps)
+        rate = inter / (t_mv * 1e-3)
+        kernels["matvec64"] = {
+            "bound": "alu", "achieved": rate * OPS_PER_INTERACTION / 1e12,
+            "peak": VALU_OPS_PER_S / 1e12, "unit": "TFLOP/s", "ms": t_mv,
+            "interactions_per_s": rate,
+            "r64_interactions_per_s": VALU_OPS_PER_S / OPS_PER_INTERACTION}
+        R.rbf_matvec_device(h, wv, yv, R.RBF_MIXED, R.RBF_ORDER_SORTED, stream)
+        t_mv32 = event_time(torch, stream, lambda: R.rbf_matvec_device(
+            h, wv, yv, R.RBF_MIXED, R.RBF_ORDER_SORTED, stream), args.kernel_reps)
+        kernels["matvec32"] = {"ms": t_mv32, "interactions_per_s": inter / (t_mv32 * 1e-3)}
+        R.rbf_precond_apply_device(h, wv, yv, R.RBF_FP64, R.RBF_ORDER_SORTED, stream)
+        t_ra = event_time(torch, stream, lambda: R.rbf_precond_apply_device(
+            h, wv, yv, R.RBF_FP64, R.RBF_ORDER_SORTED, stream), args.kernel_reps)
+        zbytes = float(np.sum(no * nc)) * 8.0
+        bytes_ = zbytes + 16.0 * w.n
+        kernels["rasm_apply64"] = {
+            "bound": "hbm", "achieved": bytes_ / (t_ra * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "ms": t_ra, "bytes_per_launch": bytes_}
+    finally:
+        R.rbf_destroy(h)
+    for k in kernels.values():
+        if "peak" in k:
+            k["frac"] = k["achieved"] / k["peak"]
+    # the dominant kernel: the largest share of the FP64 step
+    share = {
+        "precond_setup64": kernels["precond_setup64"]["ms"],
+        "matvec64": kernels["matvec64"]["ms"] * last["matvecs64"],
+        "rasm_apply64": kernels["rasm_apply64"]["ms"] * last["precond_applies"],
+    }
+    dom = max(share, key=share.get)
+    k = kernels[dom]
+    roofline = {"kernel": dom, "bound": k["bound"], "achieved": k["achieved"], "peak": k["peak"],
+                "unit": k["unit"], "frac": k["frac"], "traffic": None,
+                "step_share_ms": share}
+
+    # ---- mixed precision: time to the same tolerance ---------------------------
+    mixed = None
+    if not args.no_mixed:
+        mopts = R.default_opts(rtol=w.rtol, precision=R.RBF_MIXED, stream=stream)
+        lam64 = d_lam.clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+        try:
+            R.rbf_precond_setup(h, R.RBF_MIXED, stream)
+            minfo, mst = R.rbf_solve_device(h, d_lam, mopts, ok=(R.RBF_OK, R.RBF_ENOCONV))
+        finally:
+            R.rbf_destroy(h)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t1
+        werr = float(torch.linalg.norm(d_lam - lam64) / torch.linalg.norm(lam64))
+        mixed = {"s_to_tol": tm, "status": R.status_name(mst),
+                 "iterations_inner": minfo.iterations, "outer": minfo.outer_iterations,
+                 "rel_residual": minfo.rel_residual, "weight_rel_diff_vs_fp64": werr}
+        log("mixed", mixed)
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline: oracle on a", args.cpu_side, "lattice")
+        cpu = cpu_baseline(w, args.cpu_side)
+        log("cpu", cpu)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{w.name}: N={w.n} jittered {w.n_side}x{w.n_side} lattice on "
+                                f"[-1,1]^2, h/sigma={w.h_over_sigma}, cutoff 6 sigma, RASM 3x3 "
+                                f"cells, GMRES(30) to {w.rtol:g}; step = binning + local "
+                                "factorisations + solve"),
+                   "n": w.n, "rtol": w.rtol, "interactions_per_matvec": inter},
+        "s_to_tol_fp64": ms_step / 1e3,
+        "fp64_solve": {k: last[k] for k in ("iterations", "restarts", "rel_residual",
+                                            "t_pcsetup", "t_matmult", "t_matsolve",
+                                            "t_vecmdot", "t_other", "matvecs64",
+                                            "precond_applies")},
+        "mixed": mixed,
+        "p99_latency_s": None,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

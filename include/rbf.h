@@ -1,0 +1,189 @@
+/* rbf.h -- C ABI of the MI355X Gaussian radial-basis-function interpolation
+ * library: cell binning, cutoff-truncated Gaussian matvec, restricted additive
+ * Schwarz (RASM) preconditioner with dense local Cholesky solves, and
+ * right-preconditioned restarted GMRES, in plain FP64 or FP32-inner/FP64-outer
+ * mixed precision, all on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Yokota, Barba and Knepley, "PetRBF -- A parallel O(N)
+ * algorithm for radial basis function interpolation":
+ *   - the interpolation problem and its linear system: Section 2.1, eqs. rbf1
+ *     and rbf2 (the Gaussian needs no polynomial block);
+ *   - the normalised 2-D Gaussian A_ij = exp(-|x_i-x_j|^2/(2 sigma^2)) /
+ *     (2 pi sigma^2) and the matvec that neglects distant pairs: Section 2.3;
+ *   - RASM, z = sum_i Rt_i^T A_i^{-1} R_i v, used as a preconditioner for
+ *     GMRES: Section 2.2, eq. rasm and the matrix M^{-1} that follows it.
+ *
+ * Conventions for every function:
+ *   - extern "C", no exceptions cross the boundary, nothing aborts or exits;
+ *     every failure is a status code, with detail in rbf_last_error().
+ *   - Points are 2-D, passed as n x 2 row-major doubles (x0, y0, x1, y1, ...).
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *     memory of the current device.  The caller owns every buffer it passes in;
+ *     the library owns everything reachable from an rbf_problem handle.
+ *   - Vectors indexed by point are in the caller's ORIGINAL point order unless
+ *     an argument says RBF_ORDER_SORTED (the library's cell-binned order,
+ *     sorted by (cell index, original index)).
+ *   - stream: a hipStream_t passed as void*; NULL means the default stream.
+ *     Calls that take host buffers synchronise that stream before returning.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently.
+ */
+#ifndef RBF_H
+#define RBF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbf_problem rbf_problem;   /* opaque; created by rbf_setup* */
+
+typedef enum {
+    RBF_OK = 0,
+    RBF_EINVAL = 1,       /* bad argument: n < 1, sigma/cutoff <= 0 or non-finite,
+                             overlap < 0, NaN/Inf in points or values, NULL pointer */
+    RBF_EDUPLICATE = 2,   /* two bit-identical points: the Gaussian matrix is then
+                             singular (Section 2.1 needs distinct nodes) */
+    RBF_ENOMEM = 3,       /* device allocation failed or max_device_bytes exceeded */
+    RBF_EDEVICE = 4,      /* a HIP runtime error */
+    RBF_ENOTPD = 5,       /* a local block failed its Cholesky factorisation */
+    RBF_ENOCONV = 6,      /* iteration limit reached; best iterate is returned */
+    RBF_EBREAKDOWN = 7,   /* Arnoldi breakdown with a residual above tolerance */
+    RBF_ENAN = 8,         /* a NaN or Inf appeared in an iterate */
+    RBF_ESTATE = 9,       /* call out of order (e.g. evaluate before a solve) */
+    RBF_ELIMIT = 10       /* problem exceeds a documented size limit (a cell with
+                             more points than RBF_MAX_CELL_POINTS, or a local
+                             block larger than RBF_MAX_BLOCK) */
+} rbf_status;
+
+typedef enum { RBF_FP64 = 0, RBF_MIXED = 1 } rbf_precision;
+typedef enum { RBF_ORDER_ORIGINAL = 0, RBF_ORDER_SORTED = 1 } rbf_order;
+
+#define RBF_MAX_BLOCK 1536          /* largest overlapping-subdomain size */
+#define RBF_MAX_CELL_POINTS 1536    /* largest number of points in one cell */
+
+typedef struct {
+    int restart;            /* GMRES restart length m (default 30) */
+    int max_iters;          /* total Arnoldi steps over all cycles (default 10000) */
+    double rtol;            /* stop when ||f - A lambda||_2 / ||f||_2 <= rtol, with
+                               A the cutoff-truncated matrix (default 1e-10) */
+    rbf_precision precision;
+    double inner_rtol;      /* RBF_MIXED: inner GMRES relative tolerance (default 1e-4) */
+    int max_outer;          /* RBF_MIXED: outer refinement steps (default 60) */
+    size_t max_device_bytes;/* 0 = no limit; else fail with RBF_ENOMEM beyond it */
+    void* stream;           /* hipStream_t for every launch of the call */
+} rbf_solve_opts;
+
+typedef struct {
+    int iterations;         /* Arnoldi steps (inner steps in RBF_MIXED) */
+    int outer_iterations;   /* refinement steps (RBF_MIXED), else 0 */
+    int restarts;           /* GMRES cycles completed */
+    double rel_residual;    /* final true relative residual, FP64 */
+    /* phase seconds, named after the paper's time breakdown (Section 4.2) */
+    double t_init, t_pcsetup, t_matmult, t_matsolve, t_vecmdot, t_other;
+    long long interactions_per_matvec;  /* in-cutoff ordered pairs, i = j included;
+                                           -1 until rbf_neighbor_counts has run */
+    int matvecs64;          /* FP64 matvec applications in this call */
+    int matvecs32;          /* FP32 matvec applications (RBF_MIXED inner solves) */
+    int precond_applies;    /* RASM applications */
+    size_t device_bytes;    /* bytes the handle holds on the device */
+    int history_len;        /* entries in history (valid until the next call) */
+    const double* history;  /* true relative residual at each cycle start and end */
+} rbf_solve_info;
+
+/* Set opts to the defaults listed above. */
+void rbf_default_opts(rbf_solve_opts* opts);
+
+/* Build a problem from host arrays (Section 2.1: points x_j, data f_j):
+ * bins the points into square cells of side `cutoff` (the non-overlapping
+ * subdomains), sorts them by cell, and checks them.  `overlap` is the number of
+ * cell layers added around a cell to form its overlapping subdomain (1 gives the
+ * 3x3 block of cells).  sigma is the Gaussian width; pairs farther apart than
+ * `cutoff` are dropped from the matvec.  values may be NULL (then solve needs a
+ * right-hand side through rbf_set_values).  Inputs are copied; they may be
+ * freed on return.  Errors: RBF_EINVAL, RBF_EDUPLICATE, RBF_ENOMEM, RBF_EDEVICE,
+ * RBF_ELIMIT. */
+rbf_status rbf_setup(const double* points, const double* values, long long n,
+                     double sigma, double cutoff, int overlap, rbf_problem** out);
+
+/* As rbf_setup, with device arrays read on `stream`. */
+rbf_status rbf_setup_device(const double* d_points, const double* d_values, long long n,
+                            double sigma, double cutoff, int overlap, void* stream,
+                            rbf_problem** out);
+
+/* Replace the right-hand side f (n values, original order, device or host). */
+rbf_status rbf_set_values(rbf_problem* p, const double* values, int values_on_device,
+                          void* stream);
+
+/* Factor every local block (Section 2.2: A_i on the overlapping subdomain,
+ * untruncated Gaussian, dense Cholesky) and keep the centre rows of its inverse.
+ * precision RBF_MIXED stores them in FP32.  rbf_solve calls this when needed;
+ * calling it first separates its time.  Errors: RBF_ENOTPD, RBF_ENOMEM. */
+rbf_status rbf_precond_setup(rbf_problem* p, rbf_precision precision, void* stream);
+
+/* Solve A lambda = f (Section 2.1) by GMRES(m) right-preconditioned with RASM
+ * (Section 2.2).  lambda0: initial guess, original order, host, or NULL for 0.
+ * lambda_out: n host doubles, original order.  info may be NULL.
+ * On RBF_ENOCONV lambda_out holds the last iterate and info its residual. */
+rbf_status rbf_solve(rbf_problem* p, const rbf_solve_opts* opts, const double* lambda0,
+                     double* lambda_out, rbf_solve_info* info);
+
+/* As rbf_solve with device buffers (original order). */
+rbf_status rbf_solve_device(rbf_problem* p, const rbf_solve_opts* opts,
+                            const double* d_lambda0, double* d_lambda_out,
+                            rbf_solve_info* info);
+
+/* Interpolant s(x) = sum_j lambda_j phi(|x - x_j|) (eq. rbf1 without the
+ * polynomial part) at m targets (m x 2 host doubles) with the weights of the
+ * last successful solve, over sources within the cutoff.  Targets outside the
+ * point set's grid are clamped to the border cells.  Errors: RBF_ESTATE if no
+ * solve has succeeded. */
+rbf_status rbf_evaluate(const rbf_problem* p, const double* targets, long long m,
+                        double* out);
+rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, long long m,
+                               double* d_out, void* stream);
+
+/* Release everything the handle owns (NULL is ignored). */
+void rbf_destroy(rbf_problem* p);
+
+/* ---- single steps of the method, for measurement and parity checks -------- */
+
+/* Grid: out4 = {x0, y0, L, 1/L} (origin = minimum coordinates, side L = cutoff),
+ * ncxy = {ncx, ncy}. */
+rbf_status rbf_grid(const rbf_problem* p, double* out4, long long* ncxy);
+
+/* Binning (host outputs, any may be NULL): cell_of[i] for each original point,
+ * perm[s] = original index of the s-th sorted point, cell_start[c] for
+ * c = 0..ncx*ncy (ncx*ncy + 1 entries, int32). */
+rbf_status rbf_binning(const rbf_problem* p, int* cell_of, int* perm, int* cell_start);
+
+/* Number of in-cutoff sources of every point (original order, host), and the
+ * total (the interactions of one matvec). */
+rbf_status rbf_neighbor_counts(rbf_problem* p, int* nnb, long long* total);
+
+/* y = A w (Section 2.3, truncated normalised Gaussian) on device vectors in the
+ * given order; precision RBF_MIXED runs the FP32 kernel (FP64 in and out). */
+rbf_status rbf_matvec_device(rbf_problem* p, const double* d_w, double* d_y,
+                             rbf_precision precision, rbf_order order, void* stream);
+
+/* z = M^{-1} v, RASM (Section 2.2, eq. rasm), on device vectors; builds the
+ * preconditioner of that precision first if needed. */
+rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d_z,
+                                    rbf_precision precision, rbf_order order,
+                                    void* stream);
+
+/* Members of cell c's overlapping subdomain (original indices, neighbour cells
+ * in (dy, dx) order first, the cell's own points last) and the stored centre
+ * rows Z_c of the inverse of its local matrix, row-major ncentre x nomega, as
+ * doubles.  Pass NULL to query the sizes only. */
+rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precision,
+                             long long* members, double* z_rows, int* nomega,
+                             int* ncentre);
+
+const char* rbf_status_string(rbf_status s);
+const char* rbf_last_error(void);   /* detail of the calling thread's last error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1111 @@
+// capi.cpp -- host driver and C ABI (include/rbf.h).
+//
+// Runs the whole method on one GPU: binning, RASM setup, right-preconditioned
+// GMRES(m) (Section 2.2) in FP64 or as FP32 inner solves inside an FP64
+// residual-correction loop, and evaluation of the interpolant (eq. rbf1).
+// Every step is a kernel from binning.hip / matvec.hip / precond.hip /
+// krylov.hip; the host only sizes buffers, launches, and runs the m x m
+// Hessenberg least-squares recurrence (Givens rotations), which is O(m) work
+// per Arnoldi step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rbf.h"
+#include "rbf_internal.hpp"
+
+using rbf::Grid;
+
+static constexpr double kPi = 3.14159265358979323846;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rbf_status fail(rbf_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                \
+    } while (0)
+
+#define RBF_TRY(expr)                    \
+    do {                                 \
+        rbf_status s_ = (expr);          \
+        if (s_ != RBF_OK) return s_;     \
+    } while (0)
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double sec() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+// device buffer owned by a problem
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct rbf_problem {
+    int device = 0;
+    long long n = 0;
+    double sigma = 0, cutoff = 0;
+    int overlap = 1;
+    Grid g{};
+    long long ncells = 0;
+    size_t bytes = 0;
+    size_t budget = 0;                 // 0 = unlimited
+    std::vector<DevBuf> bufs;
+
+    // sorted data
+    double *xs = nullptr, *ys = nullptr, *fs = nullptr;
+    float *xr = nullptr, *yr = nullptr;
+    int *perm = nullptr, *cell_of = nullptr, *cell_start = nullptr;
+    bool have_values = false;
+    double sc32 = 0;                   // FP32 coordinate scale
+    long long interactions = -1;
+
+    // preconditioner
+    std::vector<int> cs_host;          // cell_start on host
+    std::vector<int> n_omega, n_c;     // per cell
+    std::vector<long long> zoff_host;
+    long long* zoff = nullptr;
+    int np_max = 0;
+    double* Z64 = nullptr;
+    float* Z32 = nullptr;
+    double t_pcsetup64 = 0, t_pcsetup32 = 0;
+    int shifted_blocks32 = 0;
+
+    // solve workspace
+    int ws_m = 0;
+    double *V = nullptr, *w = nullptr, *z = nullptr, *r = nullptr, *x = nullptr, *d = nullptr;
+    double* rhs = nullptr;
+    double *partial = nullptr, *hdev = nullptr;
+    int* flag = nullptr;
+    double* lam = nullptr;             // last solution, sorted order
+    bool solved = false;
+    std::vector<double> history;
+
+    rbf_status alloc(void** out, size_t bytes_) {
+        if (budget && this->bytes + bytes_ > budget)
+            return fail(RBF_ENOMEM, "device memory budget of %zu bytes exceeded (%zu + %zu)",
+                        budget, this->bytes, bytes_);
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes_ ? bytes_ : 1);
+        if (e != hipSuccess)
+            return fail(RBF_ENOMEM, "hipMalloc(%zu): %s", bytes_, hipGetErrorString(e));
+        bufs.push_back({p, bytes_});
+        this->bytes += bytes_;
+        *out = p;
+        return RBF_OK;
+    }
+    template <typename T>
+    rbf_status alloc_n(T** out, long long count) {
+        return alloc(reinterpret_cast<void**>(out), sizeof(T) * (size_t)(count > 0 ? count : 1));
+    }
+    void release(void* p) {
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (bufs[i].p == p) {
+                (void)hipFree(p);
+                bytes -= bufs[i].bytes;
+                bufs.erase(bufs.begin() + i);
+                return;
+            }
+    }
+    ~rbf_problem() {
+        for (auto& b : bufs) (void)hipFree(b.p);
+    }
+
+    rbf::MatvecArgs mv_args() const {
+        rbf::MatvecArgs a;
+        a.sx = xs;
+        a.sy = ys;
+        a.scell = cell_start;
+        a.tx = xs;
+        a.ty = ys;
+        a.tcell = cell_start;
+        a.g = g;
+        a.rc2 = cutoff * cutoff;
+        a.mk = -1.0 / (2.0 * sigma * sigma);
+        a.norm = 1.0 / (2.0 * kPi * sigma * sigma);
+        return a;
+    }
+    rbf::Matvec32Args mv32_args() const {
+        rbf::Matvec32Args a;
+        a.sx = xr;
+        a.sy = yr;
+        a.scell = cell_start;
+        a.g = g;
+        a.Ls = (float)(g.L * sc32);
+        a.rc2s = (float)(cutoff * cutoff * sc32 * sc32);
+        a.norm = 1.0 / (2.0 * kPi * sigma * sigma);
+        return a;
+    }
+    rbf::PrecondArgs pc_args() const {
+        rbf::PrecondArgs a;
+        a.xs = xs;
+        a.ys = ys;
+        a.cell_start = cell_start;
+        a.g = g;
+        a.overlap = overlap;
+        a.mk = -1.0 / (2.0 * sigma * sigma);
+        a.norm = 1.0 / (2.0 * kPi * sigma * sigma);
+        a.zoff = zoff;
+        a.np_max = np_max;
+        a.ncells = ncells;
+        return a;
+    }
+};
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool finite(double v) { return std::isfinite(v); }
+
+rbf_status check_args(long long n, double sigma, double cutoff, int overlap) {
+    if (n < 1) return fail(RBF_EINVAL, "n must be >= 1 (got %lld)", n);
+    if (n > 2000000000LL) return fail(RBF_ELIMIT, "n = %lld exceeds 2e9", n);
+    if (!(sigma > 0) || !finite(sigma)) return fail(RBF_EINVAL, "sigma must be finite and > 0");
+    if (!(cutoff > 0) || !finite(cutoff)) return fail(RBF_EINVAL, "cutoff must be finite and > 0");
+    if (overlap < 0) return fail(RBF_EINVAL, "overlap must be >= 0");
+    if (overlap > 16) return fail(RBF_ELIMIT, "overlap must be <= 16");
+    return RBF_OK;
+}
+
+// The setup pipeline on device arrays d_pts (n x 2) and d_vals (n or NULL).
+rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals, hipStream_t st) {
+    const long long n = p->n;
+    double* work;
+    double* mm;
+    int* bad;
+    RBF_TRY(p->alloc_n(&work, 4 * rbf::kReduceBlocks + 4));
+    mm = work + 4 * rbf::kReduceBlocks;
+    RBF_TRY(p->alloc_n(&bad, 4));
+    HIP_TRY(hipMemsetAsync(bad, 0, 4 * sizeof(int), st));
+    HIP_TRY(rbf::launch_minmax(d_pts, d_vals, n, work, mm, bad, st));
+    double h_mm[4];
+    int h_bad = 0;
+    HIP_TRY(hipMemcpyAsync(h_mm, mm, sizeof h_mm, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h_bad) return fail(RBF_EINVAL, "points or values contain NaN or Inf");
+    Grid& g = p->g;
+    g.x0 = h_mm[0];
+    g.y0 = h_mm[1];
+    g.L = p->cutoff;
+    g.invL = 1.0 / p->cutoff;
+    double fx = std::floor((h_mm[2] - h_mm[0]) * g.invL);
+    double fy = std::floor((h_mm[3] - h_mm[1]) * g.invL);
+    if (!(fx < 1e9) || !(fy < 1e9) || (fx + 1) * (fy + 1) > 1e9)
+        return fail(RBF_EINVAL, "cell grid too large: %.0f x %.0f cells (cutoff too small)",
+                    fx + 1, fy + 1);
+    g.ncx = (int)fx + 1;
+    g.ncy = (int)fy + 1;
+    p->ncells = g.ncells();
+    const long long nc = p->ncells;
+
+    int *counts, *slot, *tmp, *scan_work;
+    RBF_TRY(p->alloc_n(&p->cell_of, n));
+    RBF_TRY(p->alloc_n(&p->perm, n));
+    RBF_TRY(p->alloc_n(&p->cell_start, nc + 1));
+    RBF_TRY(p->alloc_n(&counts, nc));
+    RBF_TRY(p->alloc_n(&slot, n));
+    RBF_TRY(p->alloc_n(&tmp, n));
+    RBF_TRY(p->alloc_n(&scan_work, rbf::scan_work_ints(nc)));
+    HIP_TRY(hipMemsetAsync(counts, 0, sizeof(int) * nc, st));
+    HIP_TRY(rbf::launch_cell_count(d_pts, n, g, p->cell_of, slot, counts, st));
+    HIP_TRY(rbf::launch_exclusive_scan(counts, p->cell_start, nc, scan_work, st));
+    HIP_TRY(rbf::launch_scatter(p->cell_of, slot, p->cell_start, n, tmp, st));
+    HIP_TRY(rbf::launch_sort_cells(tmp, p->cell_start, nc, p->perm, RBF_MAX_CELL_POINTS, bad + 1,
+                                   st));
+    RBF_TRY(p->alloc_n(&p->xs, n));
+    RBF_TRY(p->alloc_n(&p->ys, n));
+    RBF_TRY(p->alloc_n(&p->fs, n));
+    RBF_TRY(p->alloc_n(&p->xr, n));
+    RBF_TRY(p->alloc_n(&p->yr, n));
+    // FP32 coordinates: scaled so that |dx_s|^2 = |dx|^2 log2(e) / (2 sigma^2)
+    p->sc32 = std::sqrt(1.4426950408889634 / 2.0) / p->sigma;
+    HIP_TRY(rbf::launch_gather(d_pts, d_vals, p->perm, p->cell_of, n, g, p->sc32, p->xs, p->ys,
+                               p->fs, p->xr, p->yr, st));
+    HIP_TRY(rbf::launch_dup_check(p->xs, p->ys, p->cell_start, nc, bad + 2, st));
+    int h_flags[4];
+    HIP_TRY(hipMemcpyAsync(h_flags, bad, sizeof h_flags, hipMemcpyDeviceToHost, st));
+    p->cs_host.resize(nc + 1);
+    HIP_TRY(hipMemcpyAsync(p->cs_host.data(), p->cell_start, sizeof(int) * (nc + 1),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h_flags[1])
+        return fail(RBF_ELIMIT, "%d cells hold more than %d points", h_flags[1],
+                    RBF_MAX_CELL_POINTS);
+    if (h_flags[2]) return fail(RBF_EDUPLICATE, "two points are bit-identical");
+    p->have_values = d_vals != nullptr;
+    p->release(counts);
+    p->release(slot);
+    p->release(tmp);
+    p->release(scan_work);
+    p->release(work);
+    // keep `bad` as a flag word for later use
+    p->flag = bad;
+
+    // per-cell block sizes (host): members of the (2*ov+1)^2 block, own points
+    const int ov = p->overlap;
+    p->n_omega.assign(nc, 0);
+    p->n_c.assign(nc, 0);
+    int maxo = 0;
+    for (long long c = 0; c < nc; ++c) {
+        int cx = (int)(c % g.ncx), cy = (int)(c / g.ncx);
+        int xlo = std::max(cx - ov, 0), xhi = std::min(cx + ov, g.ncx - 1);
+        long long tot = 0;
+        for (int dy = -ov; dy <= ov; ++dy) {
+            int ny = cy + dy;
+            if (ny < 0 || ny >= g.ncy) continue;
+            tot += p->cs_host[(long long)ny * g.ncx + xhi + 1] - p->cs_host[(long long)ny * g.ncx + xlo];
+        }
+        int own = p->cs_host[c + 1] - p->cs_host[c];
+        p->n_c[c] = own;
+        p->n_omega[c] = (int)std::min<long long>(tot, 1 << 30);
+        if (own > 0) maxo = std::max(maxo, p->n_omega[c]);
+    }
+    p->np_max = (maxo + 31) / 32 * 32;
+    return RBF_OK;
+}
+
+rbf_status create(const double* pts, const double* vals, bool on_device, long long n,
+                  double sigma, double cutoff, int overlap, hipStream_t st, rbf_problem** out) {
+    if (!out) return fail(RBF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!pts) return fail(RBF_EINVAL, "points is NULL");
+    RBF_TRY(check_args(n, sigma, cutoff, overlap));
+    rbf_problem* p = new (std::nothrow) rbf_problem();
+    if (!p) return fail(RBF_ENOMEM, "host allocation failed");
+    HIP_TRY(hipGetDevice(&p->device));
+    p->n = n;
+    p->sigma = sigma;
+    p->cutoff = cutoff;
+    p->overlap = overlap;
+    rbf_status s;
+    if (on_device) {
+        s = setup_impl(p, pts, vals, st);
+    } else {
+        double *dp = nullptr, *dv = nullptr;
+        s = p->alloc_n(&dp, 2 * n);
+        if (s == RBF_OK && vals) s = p->alloc_n(&dv, n);
+        if (s == RBF_OK) {
+            hipError_t e = hipMemcpyAsync(dp, pts, sizeof(double) * 2 * n, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess && vals)
+                e = hipMemcpyAsync(dv, vals, sizeof(double) * n, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) s = fail(RBF_EDEVICE, "copy to device: %s", hipGetErrorString(e));
+        }
+        if (s == RBF_OK) s = setup_impl(p, dp, dv, st);
+        if (dp) p->release(dp);
+        if (dv) p->release(dv);
+    }
+    if (s != RBF_OK) {
+        delete p;
+        return s;
+    }
+    *out = p;
+    return RBF_OK;
+}
+
+template <typename T>
+rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
+    const bool is64 = sizeof(T) == 8;
+    if (is64 ? p->Z64 != nullptr : p->Z32 != nullptr) return RBF_OK;
+    Timer tm;
+    const long long nc = p->ncells;
+    if (p->np_max > RBF_MAX_BLOCK)
+        return fail(RBF_ELIMIT, "a local block has %d points, above the limit %d", p->np_max,
+                    RBF_MAX_BLOCK);
+    if (p->zoff_host.empty()) {
+        p->zoff_host.resize(nc);
+        long long tot = 0;
+        for (long long c = 0; c < nc; ++c) {
+            p->zoff_host[c] = tot;
+            tot += (long long)p->n_c[c] * p->n_omega[c];
+        }
+        p->zoff_host.push_back(tot);
+        RBF_TRY(p->alloc_n(&p->zoff, nc + 1));
+        HIP_TRY(hipMemcpyAsync(p->zoff, p->zoff_host.data(), sizeof(long long) * (nc + 1),
+                               hipMemcpyHostToDevice, st));
+    }
+    const long long ztot = p->zoff_host[nc];
+    T* Z;
+    RBF_TRY(p->alloc_n(&Z, ztot));
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    long long slot_elems = (long long)p->np_max * p->np_max;
+    long long nslots = std::min<long long>(nc, 3LL * cus);
+    const long long max_scratch = 4LL << 30;
+    while (nslots > cus && nslots * slot_elems * (long long)sizeof(T) > max_scratch) nslots /= 2;
+    if (nslots < 1) nslots = 1;
+    T* scratch;
+    int* status;
+    rbf_status s = p->alloc_n(&scratch, nslots * slot_elems);
+    if (s != RBF_OK) {
+        p->release(Z);
+        return s;
+    }
+    s = p->alloc_n(&status, nc);
+    if (s != RBF_OK) {
+        p->release(Z);
+        p->release(scratch);
+        return s;
+    }
+    rbf::PrecondArgs a = p->pc_args();
+    hipError_t e;
+    if (is64)
+        e = rbf::launch_precond_setup64(a, reinterpret_cast<double*>(Z),
+                                        reinterpret_cast<double*>(scratch), (int)nslots, status, st);
+    else
+        e = rbf::launch_precond_setup32(a, reinterpret_cast<float*>(Z),
+                                        reinterpret_cast<float*>(scratch), (int)nslots, status, st);
+    std::vector<int> hs(nc);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hs.data(), status, sizeof(int) * nc, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    p->release(scratch);
+    p->release(status);
+    if (e != hipSuccess) {
+        p->release(Z);
+        return fail(RBF_EDEVICE, "preconditioner setup: %s", hipGetErrorString(e));
+    }
+    int bad = 0, shifted = 0;
+    long long first_bad = -1;
+    for (long long c = 0; c < nc; ++c) {
+        if (hs[c] > 0) {
+            if (first_bad < 0) first_bad = c;
+            ++bad;
+        } else if (hs[c] < 0) {
+            ++shifted;
+        }
+    }
+    if (bad) {
+        p->release(Z);
+        return fail(RBF_ENOTPD, "%d local blocks are not positive definite (first: cell %lld, pivot %d)",
+                    bad, first_bad, hs[first_bad]);
+    }
+    if (is64) {
+        p->Z64 = reinterpret_cast<double*>(Z);
+        p->t_pcsetup64 = tm.sec();
+    } else {
+        p->Z32 = reinterpret_cast<float*>(Z);
+        p->t_pcsetup32 = tm.sec();
+        p->shifted_blocks32 = shifted;
+    }
+    return RBF_OK;
+}
+
+rbf_status precond_setup(rbf_problem* p, rbf_precision prec, hipStream_t st) {
+    if (prec == RBF_FP64) return precond_setup_impl<double>(p, st);
+    if (prec == RBF_MIXED) return precond_setup_impl<float>(p, st);
+    return fail(RBF_EINVAL, "unknown precision %d", (int)prec);
+}
+
+rbf_status matvec(rbf_problem* p, rbf_precision prec, const double* w, double* y, hipStream_t st) {
+    if (prec == RBF_FP64) {
+        HIP_TRY(rbf::launch_matvec64(p->mv_args(), w, y, nullptr, st));
+    } else {
+        HIP_TRY(rbf::launch_matvec32(p->mv32_args(), w, y, st));
+    }
+    return RBF_OK;
+}
+
+rbf_status rasm(rbf_problem* p, rbf_precision prec, const double* v, double* z, hipStream_t st) {
+    RBF_TRY(precond_setup(p, prec, st));
+    if (prec == RBF_FP64) {
+        HIP_TRY(rbf::launch_rasm_apply64(p->pc_args(), p->Z64, v, z, st));
+    } else {
+        HIP_TRY(rbf::launch_rasm_apply32(p->pc_args(), p->Z32, v, z, st));
+    }
+    return RBF_OK;
+}
+
+rbf_status ensure_workspace(rbf_problem* p, int m) {
+    if (p->ws_m >= m) return RBF_OK;
+    if (p->V) {
+        p->release(p->V);
+        p->V = nullptr;
+    }
+    const long long n = p->n;
+    RBF_TRY(p->alloc_n(&p->V, (long long)(m + 1) * n));
+    if (!p->w) {
+        RBF_TRY(p->alloc_n(&p->w, n));
+        RBF_TRY(p->alloc_n(&p->z, n));
+        RBF_TRY(p->alloc_n(&p->r, n));
+        RBF_TRY(p->alloc_n(&p->x, n));
+        RBF_TRY(p->alloc_n(&p->d, n));
+        RBF_TRY(p->alloc_n(&p->rhs, n));
+        RBF_TRY(p->alloc_n(&p->partial, 64LL * rbf::kDotBlocks));
+        RBF_TRY(p->alloc_n(&p->hdev, 4 * 64));
+    }
+    p->ws_m = m;
+    return RBF_OK;
+}
+
+struct PhaseTimes {
+    double matmult = 0, matsolve = 0, vecmdot = 0, other = 0;
+    int mv64 = 0, mv32 = 0, pc = 0;
+};
+
+// ||v||^2 on device -> host
+rbf_status norm2(rbf_problem* p, const double* v, double* out_host, hipStream_t st) {
+    HIP_TRY(rbf::launch_multidot(v, 0, 1, v, p->n, p->partial, p->hdev + 192, st));
+    HIP_TRY(hipMemcpyAsync(out_host, p->hdev + 192, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return RBF_OK;
+}
+
+// One or more GMRES(m) cycles, right-preconditioned, on A x = b with x on
+// device (updated in place).  prec selects the operator and preconditioner
+// arithmetic.  Returns when the residual estimate is <= tol_abs, after
+// max_cycles cycles, or after the iteration budget.  Each cycle starts from the
+// residual b - A x with the same operator (r0, if given, is that residual for
+// the first cycle).
+struct CycleResult {
+    int iters = 0, cycles = 0;
+    double est = 0;             // last residual estimate (absolute)
+    bool breakdown = false;
+};
+
+rbf_status gmres_cycles(rbf_problem* p, rbf_precision prec, const double* b, double* x, int m,
+                        double tol_abs, int max_cycles, int iter_budget, hipStream_t st,
+                        CycleResult* res, PhaseTimes* pt, const double* r0) {
+    const long long n = p->n;
+    double* V = p->V;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
+    double hh[3 * 64 + 1];
+    for (int cyc = 0; cyc < max_cycles && res->iters < iter_budget; ++cyc) {
+        Timer t_res;
+        // r = b - A x  into V_0
+        if (r0 && cyc == 0) {   // residual of the starting x already known
+            HIP_TRY(hipMemcpyAsync(V, r0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        } else {
+            RBF_TRY(matvec(p, prec, x, p->w, st));
+            HIP_TRY(rbf::launch_sub(b, p->w, V, n, st));
+            (prec == RBF_FP64 ? pt->mv64 : pt->mv32) += 1;
+        }
+        double beta2;
+        RBF_TRY(norm2(p, V, &beta2, st));
+        pt->matmult += t_res.sec();
+        double beta = std::sqrt(beta2);
+        if (!std::isfinite(beta)) return fail(RBF_ENAN, "non-finite residual");
+        res->est = beta;
+        if (beta <= tol_abs || beta == 0.0) return RBF_OK;
+        HIP_TRY(rbf::launch_scale_by_inv(V, p->hdev + 192, V, n, st));
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int k = 0;
+        bool stop = false;
+        for (int j = 0; j < m && !stop; ++j) {
+            double* vj = V + (long long)j * n;
+            Timer t1;
+            RBF_TRY(rasm(p, prec, vj, p->z, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            double t_ms = t1.sec();
+            pt->pc += 1;
+            Timer t2;
+            RBF_TRY(matvec(p, prec, p->z, p->w, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            double t_mm = t2.sec();
+            (prec == RBF_FP64 ? pt->mv64 : pt->mv32) += 1;
+            Timer t3;
+            // classical Gram-Schmidt, twice
+            double* h1 = p->hdev;
+            double* h2 = p->hdev + 64;
+            double* hn2 = p->hdev + 128;
+            HIP_TRY(rbf::launch_multidot(V, n, j + 1, p->w, n, p->partial, h1, st));
+            HIP_TRY(rbf::launch_multi_axpy(V, n, j + 1, h1, p->w, n, -1.0, st));
+            HIP_TRY(rbf::launch_multidot(V, n, j + 1, p->w, n, p->partial, h2, st));
+            HIP_TRY(rbf::launch_multi_axpy(V, n, j + 1, h2, p->w, n, -1.0, st));
+            HIP_TRY(rbf::launch_multidot(p->w, 0, 1, p->w, n, p->partial, hn2, st));
+            HIP_TRY(rbf::launch_scale_by_inv(p->w, hn2, V + (long long)(j + 1) * n, n, st));
+            HIP_TRY(hipMemcpyAsync(hh, p->hdev, sizeof(double) * (3 * 64 + 1) - sizeof(double) * 63,
+                                   hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            pt->vecmdot += t3.sec();
+            pt->matsolve += t_ms;
+            pt->matmult += t_mm;
+            Timer t4;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[64 + i];
+            double hn = std::sqrt(hh[128]);
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+            double rho = std::hypot(a, bb);
+            if (!std::isfinite(rho)) return fail(RBF_ENAN, "non-finite Hessenberg entry");
+            cs[j] = rho > 0 ? a / rho : 1.0;
+            sn[j] = rho > 0 ? bb / rho : 0.0;
+            H[(size_t)j * m + j] = rho;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            ++res->iters;
+            k = j + 1;
+            res->est = std::fabs(gv[j + 1]);
+            if (hn == 0.0) {
+                res->breakdown = true;
+                stop = true;
+            }
+            if (res->est <= tol_abs || res->iters >= iter_budget) stop = true;
+            pt->other += t4.sec();
+        }
+        // y = H^{-1} g, u = V y, x += M^{-1} u
+        Timer t5;
+        for (int i = k - 1; i >= 0; --i) {
+            double s = gv[i];
+            for (int jj = i + 1; jj < k; ++jj) s -= H[(size_t)i * m + jj] * yv[jj];
+            yv[i] = s / H[(size_t)i * m + i];
+        }
+        HIP_TRY(hipMemcpyAsync(p->hdev, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+        HIP_TRY(rbf::launch_fill(p->w, 0.0, n, st));
+        HIP_TRY(rbf::launch_multi_axpy(V, n, k, p->hdev, p->w, n, 1.0, st));
+        pt->vecmdot += t5.sec();
+        Timer t6;
+        RBF_TRY(rasm(p, prec, p->w, p->z, st));
+        pt->pc += 1;
+        HIP_TRY(rbf::launch_axpy(1.0, p->z, x, n, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        pt->matsolve += t6.sec();
+        ++res->cycles;
+        if (res->est <= tol_abs || res->breakdown) return RBF_OK;
+    }
+    return RBF_OK;
+}
+
+rbf_status count_interactions(rbf_problem* p, int* d_nnb_sorted, hipStream_t st);
+
+rbf_status true_rel_residual(rbf_problem* p, const double* b, const double* x, double bnorm,
+                             double* rel, hipStream_t st, PhaseTimes* pt) {
+    Timer t;
+    RBF_TRY(matvec(p, RBF_FP64, x, p->w, st));
+    pt->mv64 += 1;
+    HIP_TRY(rbf::launch_sub(b, p->w, p->r, p->n, st));
+    double r2;
+    RBF_TRY(norm2(p, p->r, &r2, st));
+    *rel = std::sqrt(r2) / bnorm;
+    pt->matmult += t.sec();
+    return RBF_OK;
+}
+
+rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_lambda0,
+                      bool lambda0_on_device, const double* h_lambda0, rbf_solve_info* info) {
+    rbf_solve_opts opts;
+    rbf_default_opts(&opts);
+    if (o) opts = *o;
+    hipStream_t st = as_stream(opts.stream);
+    if (opts.restart < 1 || opts.restart > 63) return fail(RBF_EINVAL, "restart must be in [1, 63]");
+    if (!(opts.rtol >= 0)) return fail(RBF_EINVAL, "rtol must be >= 0");
+    if (opts.max_iters < 0) return fail(RBF_EINVAL, "max_iters must be >= 0");
+    if (opts.precision != RBF_FP64 && opts.precision != RBF_MIXED)
+        return fail(RBF_EINVAL, "unknown precision");
+    if (!p->have_values) return fail(RBF_ESTATE, "no right-hand side: pass values or call rbf_set_values");
+    p->budget = opts.max_device_bytes;
+    if (p->budget && p->bytes > p->budget)
+        return fail(RBF_ENOMEM, "the problem already holds %zu device bytes, above the budget %zu",
+                    p->bytes, p->budget);
+    Timer total;
+    PhaseTimes pt;
+    double t_pc = 0;
+    {
+        Timer t;
+        RBF_TRY(precond_setup(p, opts.precision, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        t_pc = t.sec();
+    }
+    const int m = opts.restart;
+    RBF_TRY(ensure_workspace(p, m));
+
+    const long long n = p->n;
+    // initial guess (sorted order)
+    if (d_lambda0 || h_lambda0) {
+        if (lambda0_on_device) {
+            HIP_TRY(rbf::launch_permute(d_lambda0, p->perm, n, p->x, st));
+        } else {
+            HIP_TRY(hipMemcpyAsync(p->r, h_lambda0, sizeof(double) * n, hipMemcpyHostToDevice, st));
+            HIP_TRY(rbf::launch_permute(p->r, p->perm, n, p->x, st));
+        }
+    } else {
+        HIP_TRY(rbf::launch_fill(p->x, 0.0, n, st));
+    }
+    double bnorm2;
+    RBF_TRY(norm2(p, p->fs, &bnorm2, st));
+    const double bnorm = std::sqrt(bnorm2);
+    p->history.clear();
+    rbf_status status = RBF_OK;
+    double rel = 0;
+    int iters = 0, cycles = 0, outer = 0;
+    if (bnorm == 0.0) {
+        HIP_TRY(rbf::launch_fill(p->x, 0.0, n, st));
+        rel = 0;
+    } else if (opts.precision == RBF_FP64) {
+        for (;;) {
+            RBF_TRY(true_rel_residual(p, p->fs, p->x, bnorm, &rel, st, &pt));
+            p->history.push_back(rel);
+            if (!std::isfinite(rel)) {
+                status = fail(RBF_ENAN, "non-finite residual");
+                break;
+            }
+            if (rel <= opts.rtol) break;
+            if (iters >= opts.max_iters) {
+                status = fail(RBF_ENOCONV, "no convergence in %d iterations (rel. residual %.3e)",
+                              iters, rel);
+                break;
+            }
+            CycleResult cr;
+            RBF_TRY(gmres_cycles(p, RBF_FP64, p->fs, p->x, m, opts.rtol * bnorm, 1,
+                                 opts.max_iters - iters, st, &cr, &pt, p->r));
+            iters += cr.iters;
+            cycles += cr.cycles;
+            if (cr.breakdown) {
+                RBF_TRY(true_rel_residual(p, p->fs, p->x, bnorm, &rel, st, &pt));
+                p->history.push_back(rel);
+                if (rel > opts.rtol)
+                    status = fail(RBF_EBREAKDOWN, "Arnoldi breakdown at residual %.3e", rel);
+                break;
+            }
+        }
+    } else {
+        // mixed: FP64 residual, FP32 inner GMRES on A d = r, FP64 update
+        for (;;) {
+            RBF_TRY(true_rel_residual(p, p->fs, p->x, bnorm, &rel, st, &pt));
+            p->history.push_back(rel);
+            if (!std::isfinite(rel)) {
+                status = fail(RBF_ENAN, "non-finite residual");
+                break;
+            }
+            if (rel <= opts.rtol) break;
+            if (outer >= opts.max_outer || iters >= opts.max_iters) {
+                status = fail(RBF_ENOCONV, "no convergence in %d outer steps (rel. residual %.3e)",
+                              outer, rel);
+                break;
+            }
+            double rnorm = rel * bnorm;
+            HIP_TRY(rbf::launch_fill(p->d, 0.0, n, st));
+            CycleResult cr;
+            // the residual is overwritten by later true-residual checks: keep a copy
+            HIP_TRY(hipMemcpyAsync(p->rhs, p->r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            RBF_TRY(gmres_cycles(p, RBF_MIXED, p->rhs, p->d, m,
+                                 std::max(opts.inner_rtol * rnorm, 0.5 * opts.rtol * bnorm), 1,
+                                 opts.max_iters - iters, st, &cr, &pt, p->rhs));
+            HIP_TRY(rbf::launch_axpy(1.0, p->d, p->x, n, st));
+            iters += cr.iters;
+            cycles += cr.cycles;
+            ++outer;
+        }
+    }
+    // keep the solution for evaluate
+    if (!p->lam) RBF_TRY(p->alloc_n(&p->lam, n));
+    HIP_TRY(hipMemcpyAsync(p->lam, p->x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    p->solved = (status == RBF_OK);
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->iterations = iters;
+        info->outer_iterations = outer;
+        info->restarts = cycles;
+        info->rel_residual = rel;
+        info->t_init = 0;
+        info->t_pcsetup = t_pc;
+        info->t_matmult = pt.matmult;
+        info->t_matsolve = pt.matsolve;
+        info->t_vecmdot = pt.vecmdot;
+        double acc = t_pc + pt.matmult + pt.matsolve + pt.vecmdot;
+        info->t_other = std::max(0.0, total.sec() - acc);
+        info->interactions_per_matvec = p->interactions;
+        info->matvecs64 = pt.mv64;
+        info->matvecs32 = pt.mv32;
+        info->precond_applies = pt.pc;
+        info->device_bytes = p->bytes;
+        info->history_len = (int)p->history.size();
+        info->history = p->history.data();
+    }
+    return status;
+}
+
+rbf_status count_interactions(rbf_problem* p, int* d_nnb_sorted, hipStream_t st) {
+    double* y;
+    RBF_TRY(p->alloc_n(&y, p->n));
+    long long* tot;
+    RBF_TRY(p->alloc_n(&tot, 1));
+    HIP_TRY(hipMemcpyAsync(y, p->fs, sizeof(double) * p->n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(rbf::launch_matvec64(p->mv_args(), p->fs, y, d_nnb_sorted, st));
+    HIP_TRY(rbf::launch_sum_counts(d_nnb_sorted, p->n, tot, st));
+    long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, tot, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    p->interactions = h;
+    p->release(y);
+    p->release(tot);
+    return RBF_OK;
+}
+
+rbf_status evaluate_impl(const rbf_problem* cp, const double* d_t, long long m, double* d_out,
+                         hipStream_t st) {
+    rbf_problem* p = const_cast<rbf_problem*>(cp);
+    if (!p->solved || !p->lam) return fail(RBF_ESTATE, "evaluate needs a successful solve first");
+    if (m == 0) return RBF_OK;
+    if (m < 0 || !d_t || !d_out) return fail(RBF_EINVAL, "bad targets");
+    const long long nc = p->ncells;
+    double* work;
+    int *flag, *cell_of, *slot, *counts, *tcs, *tperm, *scan_work;
+    double *tx, *ty, *yo;
+    float *fx, *fy;
+    RBF_TRY(p->alloc_n(&work, 4 * rbf::kReduceBlocks + 4));
+    RBF_TRY(p->alloc_n(&flag, 4));
+    HIP_TRY(hipMemsetAsync(flag, 0, 4 * sizeof(int), st));
+    HIP_TRY(rbf::launch_minmax(d_t, nullptr, m, work, work + 4 * rbf::kReduceBlocks, flag, st));
+    RBF_TRY(p->alloc_n(&cell_of, m));
+    RBF_TRY(p->alloc_n(&slot, m));
+    RBF_TRY(p->alloc_n(&counts, nc));
+    RBF_TRY(p->alloc_n(&tcs, nc + 1));
+    RBF_TRY(p->alloc_n(&tperm, m));
+    RBF_TRY(p->alloc_n(&scan_work, rbf::scan_work_ints(nc)));
+    RBF_TRY(p->alloc_n(&tx, m));
+    RBF_TRY(p->alloc_n(&ty, m));
+    RBF_TRY(p->alloc_n(&yo, m));
+    RBF_TRY(p->alloc_n(&fx, m));
+    RBF_TRY(p->alloc_n(&fy, m));
+    HIP_TRY(hipMemsetAsync(counts, 0, sizeof(int) * nc, st));
+    HIP_TRY(rbf::launch_cell_count(d_t, m, p->g, cell_of, slot, counts, st));
+    HIP_TRY(rbf::launch_exclusive_scan(counts, tcs, nc, scan_work, st));
+    HIP_TRY(rbf::launch_scatter(cell_of, slot, tcs, m, tperm, st));
+    HIP_TRY(rbf::launch_gather(d_t, nullptr, tperm, cell_of, m, p->g, p->sc32, tx, ty, nullptr, fx,
+                               fy, st));
+    rbf::MatvecArgs a = p->mv_args();
+    a.tx = tx;
+    a.ty = ty;
+    a.tcell = tcs;
+    HIP_TRY(rbf::launch_matvec64(a, p->lam, yo, nullptr, st));
+    HIP_TRY(rbf::launch_unpermute(yo, tperm, m, d_out, st));
+    int hflag = 0;
+    HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (void* q : {(void*)work, (void*)flag, (void*)cell_of, (void*)slot, (void*)counts, (void*)tcs,
+                    (void*)tperm, (void*)scan_work, (void*)tx, (void*)ty, (void*)yo, (void*)fx,
+                    (void*)fy})
+        p->release(q);
+    if (hflag) return fail(RBF_EINVAL, "targets contain NaN or Inf");
+    return RBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rbf_default_opts(rbf_solve_opts* o) {
+    if (!o) return;
+    o->restart = 30;
+    o->max_iters = 10000;
+    o->rtol = 1e-10;
+    o->precision = RBF_FP64;
+    o->inner_rtol = 1e-4;
+    o->max_outer = 60;
+    o->max_device_bytes = 0;
+    o->stream = nullptr;
+}
+
+rbf_status rbf_setup(const double* points, const double* values, long long n, double sigma,
+                     double cutoff, int overlap, rbf_problem** out) {
+    try {
+        return create(points, values, false, n, sigma, cutoff, overlap, nullptr, out);
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_setup");
+    }
+}
+
+rbf_status rbf_setup_device(const double* d_points, const double* d_values, long long n,
+                            double sigma, double cutoff, int overlap, void* stream,
+                            rbf_problem** out) {
+    try {
+        return create(d_points, d_values, true, n, sigma, cutoff, overlap, as_stream(stream), out);
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_setup_device");
+    }
+}
+
+rbf_status rbf_set_values(rbf_problem* p, const double* values, int on_device, void* stream) {
+    if (!p || !values) return fail(RBF_EINVAL, "NULL argument");
+    hipStream_t st = as_stream(stream);
+    double* src = const_cast<double*>(values);
+    double* tmp = nullptr;
+    if (!on_device) {
+        RBF_TRY(p->alloc_n(&tmp, p->n));
+        HIP_TRY(hipMemcpyAsync(tmp, values, sizeof(double) * p->n, hipMemcpyHostToDevice, st));
+        src = tmp;
+    }
+    int* flag = p->flag;
+    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+    HIP_TRY(rbf::launch_check_finite(src, p->n, flag, st));
+    HIP_TRY(rbf::launch_permute(src, p->perm, p->n, p->fs, st));
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (tmp) p->release(tmp);
+    if (h) return fail(RBF_EINVAL, "values contain NaN or Inf");
+    p->have_values = true;
+    p->solved = false;
+    return RBF_OK;
+}
+
+rbf_status rbf_precond_setup(rbf_problem* p, rbf_precision precision, void* stream) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    try {
+        return precond_setup(p, precision, as_stream(stream));
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_precond_setup");
+    }
+}
+
+rbf_status rbf_solve(rbf_problem* p, const rbf_solve_opts* opts, const double* lambda0,
+                     double* lambda_out, rbf_solve_info* info) {
+    if (!p || !lambda_out) return fail(RBF_EINVAL, "NULL argument");
+    try {
+        rbf_status s = solve_impl(p, opts, nullptr, false, lambda0, info);
+        if (s != RBF_OK && s != RBF_ENOCONV && s != RBF_EBREAKDOWN) return s;
+        hipStream_t st = as_stream(opts ? opts->stream : nullptr);
+        std::string keep = g_last_error;
+        HIP_TRY(rbf::launch_unpermute(p->x, p->perm, p->n, p->r, st));
+        HIP_TRY(hipMemcpyAsync(lambda_out, p->r, sizeof(double) * p->n, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        g_last_error = keep;
+        return s;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_solve");
+    }
+}
+
+rbf_status rbf_solve_device(rbf_problem* p, const rbf_solve_opts* opts, const double* d_lambda0,
+                            double* d_lambda_out, rbf_solve_info* info) {
+    if (!p || !d_lambda_out) return fail(RBF_EINVAL, "NULL argument");
+    try {
+        rbf_status s = solve_impl(p, opts, d_lambda0, true, nullptr, info);
+        if (s != RBF_OK && s != RBF_ENOCONV && s != RBF_EBREAKDOWN) return s;
+        hipStream_t st = as_stream(opts ? opts->stream : nullptr);
+        std::string keep = g_last_error;
+        HIP_TRY(rbf::launch_unpermute(p->x, p->perm, p->n, d_lambda_out, st));
+        g_last_error = keep;
+        return s;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_solve_device");
+    }
+}
+
+rbf_status rbf_evaluate(const rbf_problem* p, const double* targets, long long m, double* out) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    if (m < 0 || (m > 0 && (!targets || !out))) return fail(RBF_EINVAL, "bad targets");
+    if (m == 0) return p->solved ? RBF_OK : fail(RBF_ESTATE, "evaluate needs a successful solve first");
+    try {
+        rbf_problem* q = const_cast<rbf_problem*>(p);
+        double *dt, *dout;
+        RBF_TRY(q->alloc_n(&dt, 2 * m));
+        RBF_TRY(q->alloc_n(&dout, m));
+        HIP_TRY(hipMemcpy(dt, targets, sizeof(double) * 2 * m, hipMemcpyHostToDevice));
+        rbf_status s = evaluate_impl(p, dt, m, dout, nullptr);
+        if (s == RBF_OK) {
+            hipError_t e = hipMemcpy(out, dout, sizeof(double) * m, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) s = fail(RBF_EDEVICE, "copy out: %s", hipGetErrorString(e));
+        }
+        q->release(dt);
+        q->release(dout);
+        return s;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_evaluate");
+    }
+}
+
+rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, long long m,
+                               double* d_out, void* stream) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    try {
+        return evaluate_impl(p, d_targets, m, d_out, as_stream(stream));
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_evaluate_device");
+    }
+}
+
+void rbf_destroy(rbf_problem* p) { delete p; }
+
+rbf_status rbf_grid(const rbf_problem* p, double* out4, long long* ncxy) {
+    if (!p || !out4 || !ncxy) return fail(RBF_EINVAL, "NULL argument");
+    out4[0] = p->g.x0;
+    out4[1] = p->g.y0;
+    out4[2] = p->g.L;
+    out4[3] = p->g.invL;
+    ncxy[0] = p->g.ncx;
+    ncxy[1] = p->g.ncy;
+    return RBF_OK;
+}
+
+rbf_status rbf_binning(const rbf_problem* p, int* cell_of, int* perm, int* cell_start) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    if (cell_of) HIP_TRY(hipMemcpy(cell_of, p->cell_of, sizeof(int) * p->n, hipMemcpyDeviceToHost));
+    if (perm) HIP_TRY(hipMemcpy(perm, p->perm, sizeof(int) * p->n, hipMemcpyDeviceToHost));
+    if (cell_start)
+        HIP_TRY(hipMemcpy(cell_start, p->cell_start, sizeof(int) * (p->ncells + 1),
+                          hipMemcpyDeviceToHost));
+    return RBF_OK;
+}
+
+rbf_status rbf_neighbor_counts(rbf_problem* p, int* nnb, long long* total) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    try {
+        int *d_sorted, *d_orig;
+        RBF_TRY(p->alloc_n(&d_sorted, p->n));
+        RBF_TRY(p->alloc_n(&d_orig, p->n));
+        RBF_TRY(count_interactions(p, d_sorted, nullptr));
+        HIP_TRY(rbf::launch_unpermute_int(d_sorted, p->perm, p->n, d_orig, nullptr));
+        if (nnb) HIP_TRY(hipMemcpy(nnb, d_orig, sizeof(int) * p->n, hipMemcpyDeviceToHost));
+        HIP_TRY(hipDeviceSynchronize());
+        p->release(d_sorted);
+        p->release(d_orig);
+        if (total) *total = p->interactions;
+        return RBF_OK;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_neighbor_counts");
+    }
+}
+
+rbf_status rbf_matvec_device(rbf_problem* p, const double* d_w, double* d_y,
+                             rbf_precision precision, rbf_order order, void* stream) {
+    if (!p || !d_w || !d_y) return fail(RBF_EINVAL, "NULL argument");
+    if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_EINVAL, "bad precision");
+    hipStream_t st = as_stream(stream);
+    try {
+        if (order == RBF_ORDER_SORTED) return matvec(p, precision, d_w, d_y, st);
+        if (order != RBF_ORDER_ORIGINAL) return fail(RBF_EINVAL, "bad order");
+        double *ws, *ys;
+        RBF_TRY(p->alloc_n(&ws, p->n));
+        RBF_TRY(p->alloc_n(&ys, p->n));
+        HIP_TRY(rbf::launch_permute(d_w, p->perm, p->n, ws, st));
+        RBF_TRY(matvec(p, precision, ws, ys, st));
+        HIP_TRY(rbf::launch_unpermute(ys, p->perm, p->n, d_y, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        p->release(ws);
+        p->release(ys);
+        return RBF_OK;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_matvec_device");
+    }
+}
+
+rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d_z,
+                                    rbf_precision precision, rbf_order order, void* stream) {
+    if (!p || !d_v || !d_z) return fail(RBF_EINVAL, "NULL argument");
+    if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_EINVAL, "bad precision");
+    hipStream_t st = as_stream(stream);
+    try {
+        if (order == RBF_ORDER_SORTED) return rasm(p, precision, d_v, d_z, st);
+        if (order != RBF_ORDER_ORIGINAL) return fail(RBF_EINVAL, "bad order");
+        double *vs, *zs;
+        RBF_TRY(p->alloc_n(&vs, p->n));
+        RBF_TRY(p->alloc_n(&zs, p->n));
+        HIP_TRY(rbf::launch_permute(d_v, p->perm, p->n, vs, st));
+        rbf_status s = rasm(p, precision, vs, zs, st);
+        if (s == RBF_OK) {
+            hipError_t e = rbf::launch_unpermute(zs, p->perm, p->n, d_z, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) s = fail(RBF_EDEVICE, "%s", hipGetErrorString(e));
+        }
+        p->release(vs);
+        p->release(zs);
+        return s;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_precond_apply_device");
+    }
+}
+
+rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precision,
+                             long long* members, double* z_rows, int* nomega, int* ncentre) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    if (c < 0 || c >= p->ncells) return fail(RBF_EINVAL, "cell %lld out of range", c);
+    try {
+        const int no = p->n_omega[c], ncn = p->n_c[c];
+        if (nomega) *nomega = no;
+        if (ncentre) *ncentre = ncn;
+        if (members) {
+            std::vector<int> perm(p->n);
+            HIP_TRY(hipMemcpy(perm.data(), p->perm, sizeof(int) * p->n, hipMemcpyDeviceToHost));
+            const Grid& g = p->g;
+            int cx = (int)(c % g.ncx), cy = (int)(c / g.ncx), ov = p->overlap;
+            int xlo = std::max(cx - ov, 0), xhi = std::min(cx + ov, g.ncx - 1);
+            long long k = 0;
+            for (int dy = -ov; dy <= ov; ++dy) {
+                int ny = cy + dy;
+                if (ny < 0 || ny >= g.ncy) continue;
+                for (int nx = xlo; nx <= xhi; ++nx) {
+                    if (nx == cx && dy == 0) continue;
+                    long long cc = (long long)ny * g.ncx + nx;
+                    for (int s = p->cs_host[cc]; s < p->cs_host[cc + 1]; ++s) members[k++] = perm[s];
+                }
+            }
+            for (int s = p->cs_host[c]; s < p->cs_host[c + 1]; ++s) members[k++] = perm[s];
+        }
+        if (z_rows && ncn > 0) {
+            RBF_TRY(precond_setup(p, precision, nullptr));
+            const long long cnt = (long long)no * ncn;
+            if (precision == RBF_FP64) {
+                HIP_TRY(hipMemcpy(z_rows, p->Z64 + p->zoff_host[c], sizeof(double) * cnt,
+                                  hipMemcpyDeviceToHost));
+            } else {
+                std::vector<float> t(cnt);
+                HIP_TRY(hipMemcpy(t.data(), p->Z32 + p->zoff_host[c], sizeof(float) * cnt,
+                                  hipMemcpyDeviceToHost));
+                for (long long i = 0; i < cnt; ++i) z_rows[i] = t[i];
+            }
+        }
+        return RBF_OK;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_precond_block");
+    }
+}
+
+const char* rbf_status_string(rbf_status s) {
+    switch (s) {
+        case RBF_OK: return "RBF_OK";
+        case RBF_EINVAL: return "RBF_EINVAL";
+        case RBF_EDUPLICATE: return "RBF_EDUPLICATE";
+        case RBF_ENOMEM: return "RBF_ENOMEM";
+        case RBF_EDEVICE: return "RBF_EDEVICE";
+        case RBF_ENOTPD: return "RBF_ENOTPD";
+        case RBF_ENOCONV: return "RBF_ENOCONV";
+        case RBF_EBREAKDOWN: return "RBF_EBREAKDOWN";
+        case RBF_ENAN: return "RBF_ENAN";
+        case RBF_ESTATE: return "RBF_ESTATE";
+        case RBF_ELIMIT: return "RBF_ELIMIT";
+    }
+    return "RBF_UNKNOWN";
+}
+
+const char* rbf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// rbf_device.hpp -- device-side helpers shared by the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RBF_WAVE 64
+
+namespace rbf {
+
+// ---------------------------------------------------------------------------
+// exp(x) for x <= 0 in FP64, written from the standard Cody-Waite argument
+// reduction: x = n ln2 + r with n = rint(x / ln2) and |r| <= ln2/2, then
+// exp(x) = 2^n exp(r).  exp(r) is the degree-12 Taylor polynomial
+// sum_{k<=12} r^k / k!, whose truncation error is below r^13/13! < 1.8e-16
+// relative on |r| <= 0.3466.  ln2 is split into a 32-bit head (exact products
+// n*LN2_HI for |n| < 2^20) and its remainder.  The rounding to an integer uses
+// the 1.5*2^52 shift: after the fused multiply-add the low 32 bits of the sum
+// hold n in two's complement.  Valid for -700 < x <= 0 (no overflow, no
+// subnormal results); the cutoff keeps the matvec's arguments in [-18, 0].
+// The constants are derived in exact arithmetic by gen_constants.py.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_neg(double x) {
+    const double kLog2e = 0x1.71547652b82fep+0;        // 1/ln2 rounded
+    const double kShift = 0x1.8p52;                   // 1.5 * 2^52
+    const double kLn2Hi = 0x1.62e42ff000000p-1;       // ln2 to 32 significant bits
+    const double kLn2Lo = -0x1.718432a1b0e26p-35;     // ln2 - kLn2Hi, rounded
+    double t = __builtin_fma(x, kLog2e, kShift);
+    double nf = t - kShift;
+    int n = (int)__double2loint(t);
+    double r = __builtin_fma(nf, -kLn2Hi, x);
+    r = __builtin_fma(nf, -kLn2Lo, r);
+    double p = 0x1.1eed8eff8d898p-29;                  // 1/12!
+    p = __builtin_fma(p, r, 0x1.ae64567f544e4p-26);     // 1/11!
+    p = __builtin_fma(p, r, 0x1.27e4fb7789f5cp-22);     // 1/10!
+    p = __builtin_fma(p, r, 0x1.71de3a556c734p-19);     // 1/9!
+    p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-16);     // 1/8!
+    p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-13);     // 1/7!
+    p = __builtin_fma(p, r, 0x1.6c16c16c16c17p-10);     // 1/6!
+    p = __builtin_fma(p, r, 0x1.1111111111111p-7);      // 1/5!
+    p = __builtin_fma(p, r, 0x1.5555555555555p-5);      // 1/4!
+    p = __builtin_fma(p, r, 0x1.5555555555555p-3);      // 1/3!
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, n);
+}
+
+// 2^x in FP32 on the hardware transcendental unit (v_exp_f32).
+__device__ __forceinline__ float exp2_f32(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Wave-wide sum of a double (64 lanes), butterfly over lanes; every lane gets it.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RBF_WAVE);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RBF_WAVE);
+    return v;
+}
+
+// Kahan-compensated FP32 accumulator.
+struct Kahan32 {
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float v) {
+        float y = v - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
+}  // namespace rbf

@@ -1,0 +1,134 @@
+// rbf_internal.hpp -- launchers shared between the gfx950 kernels and the host
+// driver.  Every launcher enqueues on `st` and returns hipSuccess or the launch
+// error; none synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rbf {
+
+struct Grid {
+    double x0, y0, L, invL;
+    int ncx, ncy;
+    long long ncells() const { return (long long)ncx * ncy; }
+};
+
+// ---- binning (binning.hip) --------------------------------------------------
+// Reduce min/max of x and y over n interleaved points and flag non-finite
+// points or values.  out4 = {xmin, ymin, xmax, ymax}; bad = 1 if any NaN/Inf.
+// work must hold 4 * kReduceBlocks doubles.
+constexpr int kReduceBlocks = 512;
+hipError_t launch_minmax(const double* pts, const double* vals, long long n, double* work,
+                         double* out4, int* bad, hipStream_t st);
+// cell_of[i], slot[i] = arrival rank within the cell, counts[c] += 1.
+hipError_t launch_cell_count(const double* pts, long long n, Grid g, int* cell_of,
+                             int* slot, int* counts, hipStream_t st);
+// Exclusive scan of n ints into out (n + 1 entries, out[n] = total).
+// work must hold scan_work_ints(n) ints.
+long long scan_work_ints(long long n);
+hipError_t launch_exclusive_scan(const int* in, int* out, long long n, int* work,
+                                 hipStream_t st);
+// tmp[cell_start[cell_of[i]] + slot[i]] = i
+hipError_t launch_scatter(const int* cell_of, const int* slot, const int* cell_start,
+                          long long n, int* tmp, hipStream_t st);
+// perm[cell range] = tmp[cell range] sorted ascending, for every cell.
+// Also counts cells with more than max_pts points into *overflow.
+hipError_t launch_sort_cells(const int* tmp, const int* cell_start, long long ncells,
+                             int* perm, int max_pts, int* overflow, hipStream_t st);
+// Gather sorted coordinates / values and the FP32 cell-centre-relative scaled
+// coordinates (scale sc) used by the FP32 kernels.
+hipError_t launch_gather(const double* pts, const double* vals, const int* perm,
+                         const int* cell_of, long long n, Grid g, double sc, double* xs,
+                         double* ys, double* fs, float* xr, float* yr, hipStream_t st);
+// Flag bit-identical points within a cell.
+hipError_t launch_dup_check(const double* xs, const double* ys, const int* cell_start,
+                            long long ncells, int* dup, hipStream_t st);
+// dst[perm[s]] = src[s] (to original order) or dst[s] = src[perm[s]] (to sorted).
+hipError_t launch_unpermute(const double* src, const int* perm, long long n, double* dst,
+                            hipStream_t st);
+hipError_t launch_permute(const double* src, const int* perm, long long n, double* dst,
+                          hipStream_t st);
+hipError_t launch_unpermute_int(const int* src, const int* perm, long long n, int* dst,
+                                hipStream_t st);
+
+// ---- matvec (matvec.hip) ----------------------------------------------------
+struct MatvecArgs {
+    const double* sx;       // sources, sorted order
+    const double* sy;
+    const int* scell;       // source cell_start, ncells + 1
+    const double* tx;       // targets, target-sorted order
+    const double* ty;
+    const int* tcell;       // target cell_start
+    Grid g;
+    double rc2;             // cutoff^2
+    double mk;              // -1 / (2 sigma^2)
+    double norm;            // 1 / (2 pi sigma^2)
+};
+// y[t] = norm * sum_{s in 3x3 cells, d2 <= rc2} w[s] exp(mk d2); nnb may be NULL.
+hipError_t launch_matvec64(const MatvecArgs& a, const double* w, double* y, int* nnb,
+                           hipStream_t st);
+// FP32 form: coordinates are the FP32 cell-centre-relative scaled ones, with the
+// exponent folded in (e = 2^-(d_s^2)); weights read as FP64 and rounded; Kahan
+// FP32 accumulation; FP64 output.
+struct Matvec32Args {
+    const float* sx;
+    const float* sy;
+    const int* scell;
+    Grid g;
+    float Ls;               // cell side in scaled units
+    float rc2s;             // cutoff^2 in scaled units
+    double norm;
+};
+hipError_t launch_matvec32(const Matvec32Args& a, const double* w, double* y,
+                           hipStream_t st);
+
+// ---- preconditioner (precond.hip) --------------------------------------------
+struct PrecondArgs {
+    const double* xs;       // sorted coordinates
+    const double* ys;
+    const int* cell_start;
+    Grid g;
+    int overlap;
+    double mk, norm;        // Gaussian: norm * exp(mk d2)
+    const long long* zoff;  // per cell offset of Z_c (elements)
+    int np_max;             // padded block size bound (multiple of 32)
+    long long ncells;
+};
+// Build Z_c (centre rows of the inverse of the local matrix) for all cells.
+// scratch: nslots * np_max * np_max elements of T.  status[c]: 0 ok, else the
+// 1-based failing pivot; shift_level[c] (FP32 only) the diagonal shift used.
+hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scratch,
+                                  int nslots, int* status, hipStream_t st);
+hipError_t launch_precond_setup32(const PrecondArgs& a, float* Z, float* scratch,
+                                  int nslots, int* status, hipStream_t st);
+// z[own points of c] = Z_c v[members of c], every cell.
+hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const double* v,
+                               double* z, hipStream_t st);
+hipError_t launch_rasm_apply32(const PrecondArgs& a, const float* Z, const double* v,
+                               double* z, hipStream_t st);
+
+// ---- Krylov vector operations (krylov.hip) -----------------------------------
+constexpr int kDotBlocks = 1024;
+// out[k] = <V_k, w> for k < nv (V column k at V + k*ldv), deterministic
+// two-stage reduction; partial must hold kDotBlocks * nv doubles.
+hipError_t launch_multidot(const double* V, long long ldv, int nv, const double* w,
+                           long long n, double* partial, double* out, hipStream_t st);
+// w -= sum_k h[k] V_k (h on device), nv <= 64
+hipError_t launch_multi_axpy(const double* V, long long ldv, int nv, const double* h,
+                             double* w, long long n, double sign, hipStream_t st);
+// dst = src / sqrt(*nrm2)   (the squared norm on device)
+hipError_t launch_scale_by_inv(const double* src, const double* nrm2, double* dst,
+                               long long n, hipStream_t st);
+// r = f - y
+hipError_t launch_sub(const double* f, const double* y, double* r, long long n,
+                      hipStream_t st);
+// x += a * z (a host scalar)
+hipError_t launch_axpy(double a, const double* z, double* x, long long n, hipStream_t st);
+hipError_t launch_fill(double* x, double v, long long n, hipStream_t st);
+// flag = 1 if any x is NaN/Inf
+hipError_t launch_check_finite(const double* x, long long n, int* flag, hipStream_t st);
+// in-place block sum helpers used by the driver
+hipError_t launch_sum_counts(const int* nnb, long long n, long long* partial_out,
+                             hipStream_t st);
+
+}  // namespace rbf

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI library (no GPU): it loads, and it exports
+exactly the functions include/rbf.h declares; plus host logic of the kernels'
+FP64 exponential (its constants, checked in exact arithmetic)."""
+import math
+import os
+import re
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import paper_0909_5413_amd as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def built_lib():
+    if not os.path.exists(R.LIB_PATH):
+        from paper_0909_5413_amd import build
+        build.build()
+    return R.LIB_PATH
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rbf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("rbf_setup", "rbf_setup_device", "rbf_solve", "rbf_evaluate", "rbf_destroy",
+                 "rbf_status_string", "rbf_last_error"):
+        assert must in names
+    assert sorted(R.EXPORTED) == names
+
+
+def test_library_exports_every_declared_symbol(built_lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", built_lib], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (rbf_[a-z0-9_]+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_library_loads_without_gpu(built_lib):
+    L = R.lib()
+    assert L.rbf_status_string(R.RBF_ENOTPD).decode() == "RBF_ENOTPD"
+    o = R.default_opts()
+    assert o.restart == 30 and o.rtol == 1e-10 and o.precision == R.RBF_FP64
+
+
+def _fma(a, b, c):
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def _device_exp(x: float) -> float:
+    """The kernels' exp_neg algorithm step by step, every fused multiply-add
+    rounded exactly once (host emulation used to check its constants)."""
+    src = open(os.path.join(ROOT, "paper_0909_5413_amd", "csrc", "rbf_device.hpp")).read()
+    body = src[src.index("double exp_neg"):src.index("return __builtin_amdgcn_ldexp")]
+    consts = dict(re.findall(r"const double (k\w+) = ([0-9a-fA-Fx.p+-]+);", body))
+    log2e = float.fromhex(consts["kLog2e"])
+    shift = float.fromhex(consts["kShift"])
+    hi = float.fromhex(consts["kLn2Hi"])
+    lo = float.fromhex(consts["kLn2Lo"])
+    coefs = [float.fromhex(h) for h in re.findall(r"(0x[0-9a-f.]+p[+-]?\d+)\);?\s*// 1/", body)]
+    first = float.fromhex(re.search(r"double p = ([0-9a-fx.p+-]+);", body).group(1))
+    t = _fma(x, log2e, shift)
+    nf = t - shift
+    n = int(nf)
+    r = _fma(nf, -hi, x)
+    r = _fma(nf, -lo, r)
+    p = first
+    for c in coefs + [0.5, 1.0, 1.0]:
+        p = _fma(p, r, c)
+    return math.ldexp(p, n)
+
+
+def test_device_exp_constants_accurate():
+    rng = np.random.default_rng(3)
+    xs = np.concatenate([rng.uniform(-18.0, 0.0, 300), [-18.0, -1e-300, 0.0, -0.3465, -0.3467,
+                                                        -math.log(2) * 5.5]])
+    worst = 0.0
+    for x in xs:
+        got = _device_exp(float(x))
+        ref = math.exp(float(x))
+        worst = max(worst, abs(got - ref) / ref)
+    assert worst < 4e-16, worst

@@ -1,0 +1,273 @@
+"""GPU library vs CPU oracle, through the C ABI (run with -m gpu on an MI355X).
+
+Bars: bit-exact for binning and neighbour counts; componentwise
+|y_gpu - y_oracle| <= 1e-13 (|A| |w|)_i for the FP64 matvec; solved weights
+judged by the oracle's own FP64 residual; FP32 forms against bounds derived
+from FP32 rounding.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_0909_5413_amd as R
+from paper_0909_5413_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.lib()   # fails loudly if the HIP library is not built
+    return torch
+
+
+def ragged():
+    # 45 x 31 points over a non-square box, h/sigma = 1.0, cutoff 9 sigma: about
+    # 81 points per cell (two 64-column passes of the inverse rows), local blocks
+    # of up to 729 points (three 256-row passes of the factorisation update),
+    # partial border cells; local condition numbers ~3e3
+    rng = np.random.default_rng(77)
+    nx, ny = 45, 31
+    h = 2 / nx
+    xs = -1 + (np.arange(nx) + 0.5) * h
+    ys = -0.6 + (np.arange(ny) + 0.5) * h
+    X, Y = np.meshgrid(xs, ys)
+    pts = np.stack([X.ravel(), Y.ravel()], 1) + rng.uniform(-0.1 * h, 0.1 * h, (nx * ny, 2))
+    sigma = h / 1.0
+    return "ragged", pts, sigma, 9 * sigma
+
+
+def ill():
+    # h/sigma = 0.6: local blocks with condition numbers ~1e15
+    w = W.Workload("ill", 24, 0.6, seed=99)
+    return "ill", w.points(), w.sigma, w.cutoff
+
+
+def case(name):
+    if name == "ragged":
+        return ragged()
+    if name == "ill":
+        return ill()
+    w = W.WORKLOADS[name]
+    return name, w.points(), w.sigma, w.cutoff
+
+
+CASES = ["mini", "c0", "ragged"]
+ALL = CASES + ["ill"]
+
+
+@pytest.fixture(scope="module")
+def problems(torch_dev, oracle_mod):
+    out = {}
+    for name in ALL:
+        nm, pts, sigma, cutoff = case(name)
+        f = W.gaussian_vortex(pts)
+        say("setup", nm, pts.shape[0])
+        h = R.rbf_setup(pts, f, sigma, cutoff, 1)
+        P = oracle_mod.Problem(pts, sigma, cutoff, 1)
+        out[name] = (h, P, pts, f, sigma, cutoff)
+    yield out
+    for v in out.values():
+        R.rbf_destroy(v[0])
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_binning_bit_exact(problems, name):
+    say("binning", name)
+    h, P, pts, *_ = problems[name]
+    g, (ncx, ncy) = R.rbf_grid(h)
+    assert g[0] == P.x0 and g[1] == P.y0 and g[2] == P.L and g[3] == P.invL
+    assert (ncx, ncy) == (P.ncx, P.ncy)
+    cell_of, perm, cs = R.rbf_binning(h, pts.shape[0])
+    o_cell, o_perm, o_cs = P.binning()
+    assert np.array_equal(cell_of, o_cell)
+    assert np.array_equal(perm, o_perm)
+    assert np.array_equal(cs.astype(np.int64), o_cs)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_neighbour_counts_bit_exact(problems, name):
+    say("nnb", name)
+    h, P, pts, *_ = problems[name]
+    nnb, tot = R.rbf_neighbor_counts(h, pts.shape[0])
+    _, o_nnb = P.matvec(np.ones(pts.shape[0]), with_counts=True)
+    assert np.array_equal(nnb, o_nnb)
+    assert tot == int(o_nnb.sum())
+
+
+def gpu_matvec(torch, h, w, precision=R.RBF_FP64):
+    dw = torch.tensor(w, device="cuda", dtype=torch.float64)
+    dy = torch.empty_like(dw)
+    R.rbf_matvec_device(h, dw, dy, precision, R.RBF_ORDER_ORIGINAL,
+                        torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return dy.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_matvec64_parity(torch_dev, problems, name):
+    say("matvec64", name)
+    h, P, pts, *_ = problems[name]
+    w = W.random_weights(pts.shape[0], 11)
+    y = gpu_matvec(torch_dev, h, w)
+    yo = P.matvec(w)
+    scale = P.matvec(np.abs(w))          # (|A| |w|)_i, A is elementwise >= 0
+    err = np.abs(y - yo) / scale
+    assert err.max() <= 1e-13, err.max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_matvec32_accuracy(torch_dev, problems, name):
+    say("matvec32", name)
+    h, P, pts, *_ = problems[name]
+    w = W.random_weights(pts.shape[0], 12)
+    y = gpu_matvec(torch_dev, h, w, R.RBF_MIXED)
+    yo = P.matvec(w)
+    scale = P.matvec(np.abs(w))
+    # FP32 coordinates (cell-relative), FP32 exp2, compensated sum: a few 1e-6
+    # of the absolute sum; pairs within FP32 rounding of the cutoff may flip,
+    # each worth e^-18 of the peak
+    err = np.abs(y - yo) / scale
+    assert err.max() <= 2e-5, err.max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rasm_apply_parity(torch_dev, problems, name):
+    say("rasm64", name)
+    h, P, pts, *_ = problems[name]
+    P.rasm_setup()
+    v = W.random_weights(pts.shape[0], 13)
+    dv = torch_dev.tensor(v, device="cuda", dtype=torch_dev.float64)
+    dz = torch_dev.empty_like(dv)
+    R.rbf_precond_apply_device(h, dv, dz, R.RBF_FP64, R.RBF_ORDER_ORIGINAL,
+                               torch_dev.cuda.current_stream())
+    torch_dev.cuda.synchronize()
+    z = dz.cpu().numpy()
+    zo = P.rasm_apply(v)
+    # both sides solve the same ill-conditioned local systems: agreement is
+    # limited by cond(A_c) * u, cond(A_c) ~ 1e6..1e8 at these h/sigma
+    rel = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    assert rel <= 1e-7, rel
+
+
+@pytest.mark.parametrize("name", ["mini", "ragged", "ill"])
+def test_centre_rows_are_inverse_rows(problems, name):
+    """Z_c is a backward-stable set of rows of A_c^{-1}: with A_c rebuilt in numpy,
+    ||Z_c A_c - E_C|| <= c n u ||Z_c|| ||A_c|| whatever cond(A_c) is (the
+    ill-conditioned case has cond ~1e15, where no two factorisations agree
+    elementwise)."""
+    say("zrows", name)
+    h, P, pts, f, sigma, cutoff = problems[name]
+    _, (ncx, ncy) = R.rbf_grid(h)
+    from tests import bruteforce as bf
+    u = np.finfo(float).eps / 2
+    for cell in (0, ncx + 1, (ncx * ncy) // 2, ncx * ncy - 1):
+        mem, Z = R.rbf_precond_block(h, cell, R.RBF_FP64)
+        o_mem, kc, _ = P.rasm_block(cell, with_factor=False)
+        assert np.array_equal(mem, o_mem)
+        if Z.shape[0] == 0:
+            continue
+        A = bf.dense_matrix(pts[mem], sigma, None)
+        n = len(mem)
+        E = np.eye(n)[n - kc:]
+        res = np.linalg.norm(Z @ A - E, 2)
+        bound = 10 * n * u * np.linalg.norm(Z, 2) * np.linalg.norm(A, 2)
+        assert res <= bound, (cell, res, bound)
+
+
+@pytest.mark.parametrize("name,rtol", [("mini", 1e-12), ("c0", 1e-10), ("ragged", 1e-12)])
+def test_solve_fp64(problems, name, rtol):
+    say("solve64", name)
+    h, P, pts, f, *_ = problems[name]
+    o = R.default_opts(rtol=rtol)
+    lam, info, st = R.rbf_solve(h, pts.shape[0], o)
+    res = P.rel_residual(f, lam)
+    assert res <= rtol * 1.05, (res, info.as_dict())
+    _, oinfo = P.gmres(f, 30, rtol)
+    assert abs(info.iterations - oinfo.iterations) <= 2, (info.iterations, oinfo.iterations)
+    # evaluate at the nodes reproduces the data, and matches the oracle
+    s = R.rbf_evaluate(h, pts)
+    assert np.linalg.norm(s - f) <= 1.1 * rtol * np.linalg.norm(f)
+    stag = pts[:50] + 0.3 * (pts[1] - pts[0])
+    so = P.evaluate(lam, stag)
+    assert np.all(np.abs(R.rbf_evaluate(h, stag) - so) <= 1e-13 * (np.abs(so).max() + 1))
+
+
+@pytest.mark.parametrize("name", ["mini", "c0"])
+def test_solve_mixed(problems, name):
+    say("solve_mixed", name)
+    h, P, pts, f, *_ = problems[name]
+    o = R.default_opts(rtol=1e-12, precision=R.RBF_MIXED)
+    lam, info, st = R.rbf_solve(h, pts.shape[0], o)
+    res = P.rel_residual(f, lam)
+    assert res <= 1.05e-12, (res, info.as_dict())
+    xo, _ = P.gmres(f, 30, 1e-12)
+    werr = np.linalg.norm(lam - xo) / np.linalg.norm(xo)
+    say("mixed weight error vs oracle", name, werr, "outer", info.outer_iterations)
+
+
+def test_determinism(torch_dev, problems):
+    say("determinism")
+    h, P, pts, f, *_ = problems["c0"]
+    w = W.random_weights(pts.shape[0], 21)
+    assert np.array_equal(gpu_matvec(torch_dev, h, w), gpu_matvec(torch_dev, h, w))
+    o = R.default_opts(rtol=1e-10)
+    a, _, _ = R.rbf_solve(h, pts.shape[0], o)
+    b, _, _ = R.rbf_solve(h, pts.shape[0], o)
+    assert np.array_equal(a, b)
+
+
+def test_order_invariance(problems):
+    say("order invariance")
+    _, P, pts, f, sigma, cutoff = problems["mini"]
+    rng = np.random.default_rng(5)
+    p = rng.permutation(pts.shape[0])
+    h2 = R.rbf_setup(pts[p], f[p], sigma, cutoff, 1)
+    try:
+        lam2, _, _ = R.rbf_solve(h2, pts.shape[0], R.default_opts(rtol=1e-12))
+    finally:
+        R.rbf_destroy(h2)
+    lam = np.empty_like(lam2)
+    lam[p] = lam2
+    assert P.rel_residual(f, lam) <= 1.05e-12
+
+
+def test_error_codes(torch_dev):
+    say("errors")
+    w = W.Workload("t", 20, 0.8)
+    pts = w.points()
+    f = w.values(pts)
+    bad = pts.copy()
+    bad[4] = bad[11]
+    with pytest.raises(R.RbfError) as e:
+        R.rbf_setup(bad, f, w.sigma, w.cutoff)
+    assert e.value.status == R.RBF_EDUPLICATE
+    bad = pts.copy()
+    bad[2, 0] = np.inf
+    with pytest.raises(R.RbfError) as e:
+        R.rbf_setup(bad, f, w.sigma, w.cutoff)
+    assert e.value.status == R.RBF_EINVAL
+    with pytest.raises(R.RbfError) as e:
+        R.rbf_setup(pts, f, -1.0, w.cutoff)
+    assert e.value.status == R.RBF_EINVAL
+    h = R.rbf_setup(pts, f, w.sigma, w.cutoff)
+    try:
+        with pytest.raises(R.RbfError) as e:
+            R.rbf_evaluate(h, pts[:3])
+        assert e.value.status == R.RBF_ESTATE
+        lam, info, st = R.rbf_solve(h, w.n, R.default_opts(rtol=1e-30, max_iters=5),
+                                    ok=(R.RBF_ENOCONV,))
+        assert st == R.RBF_ENOCONV and info.iterations == 5
+        with pytest.raises(R.RbfError) as e:
+            R.rbf_solve(h, w.n, R.default_opts(max_device_bytes=1024))
+        assert e.value.status == R.RBF_ENOMEM
+    finally:
+        R.rbf_destroy(h)
