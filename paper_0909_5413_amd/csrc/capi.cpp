@@ -359,7 +359,10 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
     long long slot_elems = (long long)p->np_max * p->np_max;
-    long long nslots = std::min<long long>(nc, 3LL * cus);
+    // cells per batch (FP64: one scratch matrix per cell of a batch of three
+    // kernels; FP32: resident workgroups of the persistent kernel)
+    const long long per_cu = is64 ? 4 : 2;
+    long long nslots = std::min<long long>(nc, per_cu * cus);
     const long long max_scratch = 4LL << 30;
     while (nslots > cus && nslots * slot_elems * (long long)sizeof(T) > max_scratch) nslots /= 2;
     if (nslots < 1) nslots = 1;

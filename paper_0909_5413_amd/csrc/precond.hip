@@ -414,6 +414,494 @@ __global__ __launch_bounds__(kThreads) void k_precond_setup(PrecondArgs a, T* __
     }
 }
 
+// ===========================================================================
+// FP64 setup on the matrix cores.  Two 256-thread workgroups per CU, each
+// holding one cell's matrix at a time (n_p x n_p, lower triangle, ROW-major:
+// element (i, j) at A[i * n_p + j], so every row segment is contiguous) in a
+// private global scratch; the two workgroups hide each other's memory stalls.
+// The block-column update of the left-looking Cholesky and the substitution
+// products of the inverse rows run as v_mfma_f64_16x16x4f64 tiles fed from LDS
+// panels, the next panel being loaded into registers while the current one is
+// multiplied.  Operand layout of that instruction on gfx950: lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; the four result registers v hold
+// D[l/16 + 4v][l%16].
+// ===========================================================================
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int kT2 = 256;        // threads (4 waves)
+constexpr int kW2 = kT2 / 64;
+constexpr int kKC2 = 8;         // k per LDS panel in the update
+constexpr int kRows2 = 512;     // rows per super-block of the update
+constexpr int kRT2 = kRows2 / 16 / kW2;   // row tiles per wave (8)
+constexpr int kRPT = kRows2 / kT2;        // panel rows loaded per thread (2)
+static_assert(kRows2 % kT2 == 0, "row super-block must split evenly");
+constexpr int kZK = 64;         // k per LDS panel in the inverse-row products
+
+struct SetupLds2 {
+    union {
+        struct {
+            double P[kKC2][kRows2];      // rows of the panel, k-major
+            double Pb[kKC2][kNB];        // the block column's own rows
+        } g;
+        struct {
+            double X[kNB][kT2];          // rows being solved, one column per thread
+        } t;
+        struct {
+            double Lc[kZK][kNB + 1];
+            double Xc[kZK][kZCols + 1];
+            double acc[kNB][kZCols + 1];
+        } z;
+        struct {
+            double mx[RBF_MAX_BLOCK];
+            double my[RBF_MAX_BLOCK];
+        } coords;
+    } u;
+    double D[kNB][kNB + 1];
+    double invd[kNB];
+    int rb[kMaxRanges], re[kMaxRanges];
+    int nranges, n_omega, n_c, flag;
+};
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ d4v mfma_f64(double a, double b, d4v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// A[rows R.., cols J..J+31] -= L[rows, 0:J] L[J..J+31, 0:J]^T for one row
+// super-block (MFMA tiles; J > 0).  The tiles of rows J..J+31 also go to s.D.
+__device__ void update_block_column(double* __restrict__ A, int np, int J, int R,
+                                    SetupLds2& s) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nrow = np - R < kRows2 ? np - R : kRows2;   // multiple of 32
+    const int ntile = nrow / 16;
+    d4v acc[kRT2][2];
+#pragma unroll
+    for (int t = 0; t < kRT2; ++t) acc[t][0] = acc[t][1] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int nchunk = J / kKC2;   // J is a multiple of 32
+    constexpr int kBL = kNB * kKC2 / kT2;   // B-panel values per thread
+    static_assert(kNB * kKC2 % kT2 == 0 && kBL >= 1, "B panel must split evenly");
+    double ra[kRPT][kKC2], rb[kBL];
+    auto load = [&](int chunk) {
+        const int K = chunk * kKC2;
+#pragma unroll
+        for (int h = 0; h < kRPT; ++h) {
+            const int r = tid + kT2 * h;
+            if (r < nrow) {
+                const double* src = A + (size_t)(R + r) * np + K;
+#pragma unroll
+                for (int q = 0; q < kKC2; ++q) ra[h][q] = src[q];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < kBL; ++h) {
+            const int idx = tid + kT2 * h;   // 32 rows x kKC2 k
+            rb[h] = A[(size_t)(J + idx / kKC2) * np + K + idx % kKC2];
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int h = 0; h < kRPT; ++h) {
+            const int r = tid + kT2 * h;
+#pragma unroll
+            for (int q = 0; q < kKC2; ++q) s.u.g.P[q][r] = r < nrow ? ra[h][q] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < kBL; ++h) {
+            const int idx = tid + kT2 * h;
+            s.u.g.Pb[idx % kKC2][idx / kKC2] = rb[h];
+        }
+    };
+    load(0);
+    __syncthreads();
+    store();
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        if (ch + 1 < nchunk) load(ch + 1);
+#pragma unroll
+        for (int ks = 0; ks < kKC2 / 4; ++ks) {
+            const int kr = 4 * ks + (lane >> 4);
+            const double b0 = s.u.g.Pb[kr][lane & 15];
+            const double b1 = s.u.g.Pb[kr][16 + (lane & 15)];
+#pragma unroll
+            for (int t = 0; t < kRT2; ++t) {
+                const int tile = wave + kW2 * t;
+                if (tile < ntile) {
+                    const double a = s.u.g.P[kr][16 * tile + (lane & 15)];
+                    acc[t][0] = mfma_f64(a, b0, acc[t][0]);
+                    acc[t][1] = mfma_f64(a, b1, acc[t][1]);
+                }
+            }
+        }
+        __syncthreads();
+        if (ch + 1 < nchunk) {
+            store();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kRT2; ++t) {
+        const int tile = wave + kW2 * t;
+        if (tile < ntile) {
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rl = 16 * tile + (lane >> 4) + 4 * v;
+                    const int col = 16 * cb + (lane & 15);
+                    double* ad = A + (size_t)(R + rl) * np + J + col;
+                    const double nv = *ad - acc[t][cb][v];
+                    *ad = nv;
+                    if (R == J && rl < kNB) s.D[rl][col] = nv;
+                }
+        }
+    }
+}
+
+// Factor the 32x32 diagonal block (in s.D) in wave 0's registers (lane i holds
+// row i; broadcasts by readlane, no barriers), write it back and keep it in
+// s.D / s.invd.  Returns 0 or the failing 1-based pivot index (all threads).
+__device__ int factor_diag_block(double* __restrict__ A, int np, int J, SetupLds2& s) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        const int i = tid & 31;
+        double r[kNB];
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) r[c] = (c <= i) ? s.D[i][c] : 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int k = 0; k < kNB; ++k) {
+            const double piv = readlane_d(r[k], k);
+            if (!bad && !(piv > 0.0)) bad = k + 1;   // uniform; later values are moot
+            const double lkk = __builtin_sqrt(piv);
+            const double inv = 1.0 / lkk;
+            r[k] = (i == k) ? lkk : r[k] * inv;
+#pragma unroll
+            for (int j = k + 1; j < kNB; ++j) {
+                const double ljk = readlane_d(r[k], j);
+                r[j] = __builtin_fma(-r[k], ljk, r[j]);
+            }
+        }
+        if (tid == 0) s.flag = bad ? J + bad : 0;
+        if (!bad && tid < kNB) {
+            double* arow = A + (size_t)(J + i) * np + J;
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) {
+                if (c <= i) {
+                    arow[c] = r[c];
+                    s.D[i][c] = r[c];
+                }
+            }
+            s.invd[i] = 1.0 / r[i];
+        }
+    }
+    __syncthreads();
+    return s.flag;
+}
+
+// Rows J+32 .. np-1 of block column J: x L_JJ^T = a, one row per thread, the
+// row staged in LDS (column tid of s.u.t.X) and solved in 4 groups of 8.
+__device__ void trsm_rows(double* __restrict__ A, int np, int J, SetupLds2& s) {
+    const int tid = threadIdx.x;
+    for (int r0 = J + kNB; r0 < np; r0 += kT2) {
+        const int row = r0 + tid;
+        double* xr = A + (size_t)row * np + J;
+        if (row < np) {
+            double x[kNB];
+#pragma unroll
+            for (int q = 0; q < kNB; ++q) x[q] = xr[q];
+#pragma unroll
+            for (int q = 0; q < kNB; ++q) s.u.t.X[q][tid] = x[q];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                double y[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) y[q] = s.u.t.X[8 * g + q][tid];
+#pragma unroll
+                for (int c = 0; c < 8 * g; ++c) {
+                    const double xc = s.u.t.X[c][tid];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) y[q] = __builtin_fma(-xc, s.D[8 * g + q][c], y[q]);
+                    __asm__ volatile("" ::: "memory");
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    y[q] = y[q] * s.invd[8 * g + q];
+#pragma unroll
+                    for (int q2 = q + 1; q2 < 8; ++q2)
+                        y[q2] = __builtin_fma(-y[q], s.D[8 * g + q2][8 * g + q], y[q2]);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    s.u.t.X[8 * g + q][tid] = y[q];
+                    xr[8 * g + q] = y[q];
+                }
+                __asm__ volatile("" ::: "memory");
+            }
+        }
+    }
+}
+
+__device__ int cholesky_mfma(double* __restrict__ A, int np, SetupLds2& s) {
+    const int tid = threadIdx.x;
+    for (int J = 0; J < np; J += kNB) {
+        if (J > 0) {
+            for (int R = J; R < np; R += kRows2) update_block_column(A, np, J, R, s);
+        } else {
+            for (int idx = tid; idx < kNB * kNB; idx += kT2) {
+                const int i = idx / kNB, j = idx % kNB;
+                if (j <= i) s.D[i][j] = A[(size_t)i * np + j];
+            }
+        }
+        __syncthreads();
+        const int f = factor_diag_block(A, np, J, s);
+        if (f) return f;
+        trsm_rows(A, np, J, s);
+        __syncthreads();
+    }
+    return 0;
+}
+
+// s.u.z.acc[r][c] = rhs(r, c) - sum_k op(L)[I0 + r][k] X[k][c0 + c] over
+// k in [k_lo, k_hi) (MFMA, 8 tiles of 16x16, two per wave), then the diagonal
+// block L(I0.., I0..) into s.D / s.invd.
+//   forward (kBackward = false): op(L)[r][k] = L[r][k], rhs = E_C
+//   backward: op(L)[r][k] = L[k][r], rhs = the forward result W stored in X's
+//   place (zero above row w_lo)
+template <bool kBackward>
+__device__ void zsolve_block(const double* __restrict__ A, int np, int I0, int k_lo, int k_hi,
+                             const double* __restrict__ Zc, int ldz, int p, int c0, int ncol,
+                             int q0, int w_lo, SetupLds2& s) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rt = wave >> 1, ct0 = 2 * (wave & 1);
+    d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int nchunk = (k_hi - k_lo + kZK - 1) / kZK;
+    constexpr int kLL = kZK * kNB / kT2;      // 8 L values per thread
+    constexpr int kLX = kZK * kZCols / kT2;   // 16 X values per thread
+    static_assert(kZK * kNB % kT2 == 0 && kZK * kZCols % kT2 == 0, "panels split evenly");
+    double rl[kLL], rx[kLX];
+    auto load = [&](int chunk) {
+        const int k0 = k_lo + chunk * kZK;
+#pragma unroll
+        for (int q = 0; q < kLL; ++q) {
+            const int idx = tid + kT2 * q;
+            double v = 0.0;
+            if (kBackward) {   // L[k0 + kk][I0 + rr]: contiguous in rr
+                const int kk = idx / kNB, rr = idx % kNB;
+                if (k0 + kk < k_hi) v = A[(size_t)(k0 + kk) * np + I0 + rr];
+            } else {           // L[I0 + rr][k0 + kk]: contiguous in kk
+                const int rr = idx / kZK, kk = idx % kZK;
+                if (k0 + kk < k_hi) v = A[(size_t)(I0 + rr) * np + k0 + kk];
+            }
+            rl[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < kLX; ++q) {
+            const int idx = tid + kT2 * q;
+            const int cc = idx / kZK, kk = idx % kZK;
+            const int k = k0 + kk;
+            double v = 0.0;
+            if (cc < ncol && k < k_hi && k >= p) v = Zc[(size_t)(c0 + cc) * ldz + (k - p)];
+            rx[q] = v;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < kLL; ++q) {
+            const int idx = tid + kT2 * q;
+            if (kBackward)
+                s.u.z.Lc[idx / kNB][idx % kNB] = rl[q];
+            else
+                s.u.z.Lc[idx % kZK][idx / kZK] = rl[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kLX; ++q) {
+            const int idx = tid + kT2 * q;
+            s.u.z.Xc[idx % kZK][idx / kZK] = rx[q];
+        }
+    };
+    __syncthreads();
+    if (nchunk > 0) {
+        load(0);
+        store();
+        __syncthreads();
+        for (int ch = 0; ch < nchunk; ++ch) {
+            if (ch + 1 < nchunk) load(ch + 1);
+#pragma unroll
+            for (int ks = 0; ks < kZK / 4; ++ks) {
+                const int kr = 4 * ks + (lane >> 4);
+                const double a = s.u.z.Lc[kr][16 * rt + (lane & 15)];
+                const double b0 = s.u.z.Xc[kr][16 * ct0 + (lane & 15)];
+                const double b1 = s.u.z.Xc[kr][16 * ct0 + 16 + (lane & 15)];
+                acc0 = mfma_f64(a, b0, acc0);
+                acc1 = mfma_f64(a, b1, acc1);
+            }
+            __syncthreads();
+            if (ch + 1 < nchunk) {
+                store();
+                __syncthreads();
+            }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * rt + (lane >> 4) + 4 * v;
+            const int cc = 16 * (ct0 + h) + (lane & 15);
+            const int row = I0 + r;
+            double rhs = 0.0;
+            if (cc < ncol) {
+                if (kBackward)
+                    rhs = (row >= w_lo && row >= p) ? Zc[(size_t)(c0 + cc) * ldz + (row - p)] : 0.0;
+                else
+                    rhs = (row == q0 + c0 + cc) ? 1.0 : 0.0;
+            }
+            s.u.z.acc[r][cc] = rhs - (h ? acc1[v] : acc0[v]);
+        }
+    }
+    for (int idx = tid; idx < kNB * kNB; idx += kT2) {
+        const int i = idx / kNB, j = idx % kNB;
+        s.D[i][j] = A[(size_t)(I0 + i) * np + I0 + j];
+    }
+    __syncthreads();
+    if (tid < kNB) s.invd[tid] = 1.0 / s.D[tid][tid];
+    __syncthreads();
+}
+
+__device__ void centre_rows_mfma(const double* __restrict__ A, int np, int p, int n_omega,
+                                 int n_c, double* __restrict__ Zc, SetupLds2& s) {
+    const int tid = threadIdx.x;
+    const int q0 = np - n_c;
+    const int ib = q0 / kNB;
+    const int nblk = np / kNB;
+    for (int c0 = 0; c0 < n_c; c0 += kZCols) {
+        const int ncol = n_c - c0 < kZCols ? n_c - c0 : kZCols;
+        for (int I = ib; I < nblk; ++I) {
+            const int I0 = I * kNB;
+            zsolve_block<false>(A, np, I0, ib * kNB, I0, Zc, n_omega, p, c0, ncol, q0, 0, s);
+            if (tid < ncol) {
+                for (int r = 0; r < kNB; ++r) {
+                    double v = s.u.z.acc[r][tid];
+                    for (int r2 = 0; r2 < r; ++r2)
+                        v = __builtin_fma(-s.D[r][r2], s.u.z.acc[r2][tid], v);
+                    s.u.z.acc[r][tid] = v * s.invd[r];
+                }
+                for (int r = 0; r < kNB; ++r)
+                    if (I0 + r >= p) Zc[(size_t)(c0 + tid) * n_omega + (I0 + r - p)] = s.u.z.acc[r][tid];
+            }
+        }
+        for (int I = nblk - 1; I >= 0; --I) {
+            const int I0 = I * kNB;
+            if (I0 + kNB <= p) break;
+            zsolve_block<true>(A, np, I0, I0 + kNB, np, Zc, n_omega, p, c0, ncol, q0, ib * kNB, s);
+            if (tid < ncol) {
+                for (int r = kNB - 1; r >= 0; --r) {
+                    double v = s.u.z.acc[r][tid];
+                    for (int r2 = r + 1; r2 < kNB; ++r2)
+                        v = __builtin_fma(-s.D[r2][r], s.u.z.acc[r2][tid], v);
+                    s.u.z.acc[r][tid] = v * s.invd[r];
+                }
+                for (int r = 0; r < kNB; ++r)
+                    if (I0 + r >= p) Zc[(size_t)(c0 + tid) * n_omega + (I0 + r - p)] = s.u.z.acc[r][tid];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The FP64 setup runs as three kernels over a batch of cells, one workgroup per
+// cell and a private scratch matrix per workgroup, so that each phase gets its
+// own register allocation: assemble the local matrix, factor it, form the
+// centre rows of its inverse.  Cell of workgroup b: c0 + b.
+
+struct AssembleLds {
+    double mx[RBF_MAX_BLOCK];
+    double my[RBF_MAX_BLOCK];
+    int rb[kMaxRanges], re[kMaxRanges];
+    int nranges, n_omega, n_c, flag;
+};
+
+template <typename S>
+__device__ __forceinline__ bool load_cell_ranges(const PrecondArgs& a, long long c, S& s) {
+    if (threadIdx.x == 0) {
+        block_ranges(a.cell_start, a.g, a.overlap, c, s.rb, s.re, &s.nranges, &s.n_omega,
+                     &s.n_c);
+        s.flag = 0;
+    }
+    __syncthreads();
+    return s.n_c > 0;
+}
+
+__global__ __launch_bounds__(kT2, 2) void k_setup_assemble_f64(PrecondArgs a, long long c0,
+                                                               double* __restrict__ scratch) {
+    __shared__ AssembleLds s;
+    const long long c = c0 + blockIdx.x;
+    if (c >= a.ncells) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (!load_cell_ranges(a, c, s)) return;
+    const int n_omega = s.n_omega, nr = s.nranges;
+    const int np = (n_omega + kNB - 1) / kNB * kNB;
+    const int p = np - n_omega;
+    double* A = scratch + (size_t)blockIdx.x * a.np_max * a.np_max;
+    for (int k = tid; k < n_omega; k += kT2) {
+        const int m = member_index(s.rb, s.re, nr, k);
+        s.mx[k] = a.xs[m];
+        s.my[k] = a.ys[m];
+    }
+    __syncthreads();
+    // untruncated Gaussian, lower triangle (row-major), leading identity
+    // padding; wave w fills rows w, w + 4, ...
+    for (int i = wave; i < np; i += kW2) {
+        double* arow = A + (size_t)i * np;
+        for (int j = lane; j <= i; j += 64) {
+            double v;
+            if (i < p || j < p) {
+                v = (i == j) ? 1.0 : 0.0;
+            } else {
+                const double dx = s.mx[i - p] - s.mx[j - p];
+                const double dy = s.my[i - p] - s.my[j - p];
+                v = exp_neg(__builtin_fma(dx, dx, dy * dy) * a.mk) * a.norm;
+            }
+            arow[j] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kT2, 2) void k_setup_factor_f64(PrecondArgs a, long long c0,
+                                                             double* __restrict__ scratch,
+                                                             int* __restrict__ status) {
+    __shared__ SetupLds2 s;
+    const long long c = c0 + blockIdx.x;
+    if (c >= a.ncells) return;
+    if (!load_cell_ranges(a, c, s)) {
+        if (threadIdx.x == 0) status[c] = 0;
+        return;
+    }
+    const int np = (s.n_omega + kNB - 1) / kNB * kNB;
+    double* A = scratch + (size_t)blockIdx.x * a.np_max * a.np_max;
+    const int fail = cholesky_mfma(A, np, s);
+    if (threadIdx.x == 0) status[c] = fail;
+}
+
+__global__ __launch_bounds__(kT2, 2) void k_setup_centre_rows_f64(PrecondArgs a, long long c0,
+                                                                  double* __restrict__ Z,
+                                                                  const double* __restrict__ scratch,
+                                                                  const int* __restrict__ status) {
+    __shared__ SetupLds2 s;
+    const long long c = c0 + blockIdx.x;
+    if (c >= a.ncells || status[c] != 0) return;
+    if (!load_cell_ranges(a, c, s)) return;
+    const int n_omega = s.n_omega, n_c = s.n_c;
+    const int np = (n_omega + kNB - 1) / kNB * kNB;
+    const double* A = scratch + (size_t)blockIdx.x * a.np_max * a.np_max;
+    centre_rows_mfma(A, np, np - n_omega, n_omega, n_c, Z + a.zoff[c], s);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T* __restrict__ Z,
                                                          const double* __restrict__ v,
@@ -453,7 +941,13 @@ __global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T*
 
 hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scratch, int nslots,
                                   int* status, hipStream_t st) {
-    k_precond_setup<double><<<nslots, kThreads, 0, st>>>(a, Z, scratch, status);
+    for (long long c0 = 0; c0 < a.ncells; c0 += nslots) {
+        const long long left = a.ncells - c0;
+        const unsigned grid = (unsigned)(left < nslots ? left : nslots);
+        k_setup_assemble_f64<<<grid, kT2, 0, st>>>(a, c0, scratch);
+        k_setup_factor_f64<<<grid, kT2, 0, st>>>(a, c0, scratch, status);
+        k_setup_centre_rows_f64<<<grid, kT2, 0, st>>>(a, c0, Z, scratch, status);
+    }
     return hipGetLastError();
 }
 
