@@ -87,6 +87,9 @@ struct rbf_problem {
     bool have_values = false;
     double sc32 = 0;                   // FP32 coordinate scale
     long long interactions = -1;
+    double* etab = nullptr;            // e^{-n/128}, n < ntab (device), or NULL
+    int ntab = 0;
+    float* w32 = nullptr;              // FP32 weights workspace of the FP32 matvec
 
     // preconditioner
     std::vector<int> cs_host;          // cell_start on host
@@ -151,6 +154,8 @@ struct rbf_problem {
         a.rc2 = cutoff * cutoff;
         a.mk = -1.0 / (2.0 * sigma * sigma);
         a.norm = 1.0 / (2.0 * kPi * sigma * sigma);
+        a.etab = etab;
+        a.ntab = ntab;
         return a;
     }
     rbf::Matvec32Args mv32_args() const {
@@ -291,6 +296,20 @@ rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals,
         if (own > 0) maxo = std::max(maxo, p->n_omega[c]);
     }
     p->np_max = (maxo + 31) / 32 * 32;
+
+    // table e^{-n/128} covering the matvec's exponents down to -cutoff^2/(2 sigma^2)
+    const double xmin = p->cutoff * p->cutoff / (2.0 * p->sigma * p->sigma);
+    const double nt = std::floor(128.0 * xmin * (1.0 + 1e-12)) + 2.0;
+    if (nt <= rbf::kExpTableMax) {
+        p->ntab = (int)nt;
+        std::vector<double> tab(p->ntab);
+        for (int k = 0; k < p->ntab; ++k) tab[k] = (double)std::exp(-(long double)k / 128.0L);
+        RBF_TRY(p->alloc_n(&p->etab, p->ntab));
+        HIP_TRY(hipMemcpyAsync(p->etab, tab.data(), sizeof(double) * p->ntab, hipMemcpyHostToDevice,
+                               st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    RBF_TRY(p->alloc_n(&p->w32, n));
     return RBF_OK;
 }
 
@@ -433,7 +452,7 @@ rbf_status matvec(rbf_problem* p, rbf_precision prec, const double* w, double* y
     if (prec == RBF_FP64) {
         HIP_TRY(rbf::launch_matvec64(p->mv_args(), w, y, nullptr, st));
     } else {
-        HIP_TRY(rbf::launch_matvec32(p->mv32_args(), w, y, st));
+        HIP_TRY(rbf::launch_matvec32(p->mv32_args(), w, p->w32, y, p->n, st));
     }
     return RBF_OK;
 }

@@ -45,6 +45,28 @@ __device__ __forceinline__ double exp_neg(double x) {
     return __builtin_amdgcn_ldexp(p, n);
 }
 
+// ---------------------------------------------------------------------------
+// exp(x) for -(ntab-1)/128 <= x <= 0 from a table T[n] = e^{-n/128} (correctly
+// rounded, n = 0..ntab-1, held in LDS by the caller): with n = rint(-128 x) and
+// r = x + n/128 (|r| <= 1/256, formed exactly up to one rounding),
+// exp(x) = T[n] exp(r), exp(r) by its degree-5 Taylor polynomial (truncation
+// below r^6/720 < 5e-18).  The rounding to an integer uses the 1.5*2^52 shift.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_neg_tab(double x, const double* __restrict__ T) {
+    const double kShift = 0x1.8p52;
+    const double t = __builtin_fma(x, -128.0, kShift);
+    const double nf = t - kShift;
+    const int n = (int)__double2loint(t);
+    const double r = __builtin_fma(nf, 0x1p-7, x);
+    double p = 0x1.1111111111111p-7;                 // 1/5!
+    p = __builtin_fma(p, r, 0x1.5555555555555p-5);   // 1/4!
+    p = __builtin_fma(p, r, 0x1.5555555555555p-3);   // 1/3!
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return T[n] * p;
+}
+
 // 2^x in FP32 on the hardware transcendental unit (v_exp_f32).
 __device__ __forceinline__ float exp2_f32(float x) { return __builtin_amdgcn_exp2f(x); }
 

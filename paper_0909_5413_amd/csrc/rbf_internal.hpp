@@ -63,7 +63,11 @@ struct MatvecArgs {
     double rc2;             // cutoff^2
     double mk;              // -1 / (2 sigma^2)
     double norm;            // 1 / (2 pi sigma^2)
+    const double* etab;     // e^{-n/128}, n < ntab, or NULL (no table)
+    int ntab;
 };
+// entries of the exponential table held in LDS (covers cutoffs up to ~6.3 sigma)
+constexpr int kExpTableMax = 2560;
 // y[t] = norm * sum_{s in 3x3 cells, d2 <= rc2} w[s] exp(mk d2); nnb may be NULL.
 hipError_t launch_matvec64(const MatvecArgs& a, const double* w, double* y, int* nnb,
                            hipStream_t st);
@@ -79,8 +83,9 @@ struct Matvec32Args {
     float rc2s;             // cutoff^2 in scaled units
     double norm;
 };
-hipError_t launch_matvec32(const Matvec32Args& a, const double* w, double* y,
-                           hipStream_t st);
+// w32: n floats of workspace (the weights rounded to FP32)
+hipError_t launch_matvec32(const Matvec32Args& a, const double* w, float* w32, double* y,
+                           long long n, hipStream_t st);
 
 // ---- preconditioner (precond.hip) --------------------------------------------
 struct PrecondArgs {
