@@ -431,7 +431,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int kT2 = 256;        // threads (4 waves)
 constexpr int kW2 = kT2 / 64;
 constexpr int kKC2 = 8;         // k per LDS panel in the update
-constexpr int kRows2 = 512;     // rows per super-block of the update
+constexpr int kRows2 = 256;     // rows per super-block of the update
 constexpr int kRT2 = kRows2 / 16 / kW2;   // row tiles per wave (8)
 constexpr int kRPT = kRows2 / kT2;        // panel rows loaded per thread (2)
 static_assert(kRows2 % kT2 == 0, "row super-block must split evenly");
@@ -474,74 +474,63 @@ __device__ __forceinline__ d4v mfma_f64(double a, double b, d4v c) {
 
 // A[rows R.., cols J..J+31] -= L[rows, 0:J] L[J..J+31, 0:J]^T for one row
 // super-block (MFMA tiles; J > 0).  The tiles of rows J..J+31 also go to s.D.
+// No LDS and no barriers: the contraction index of an MFMA may be permuted as
+// long as A and B use the same permutation, so over a chunk of 16 k values lane
+// group g = l/16 owns k = K+4g .. K+4g+3 and loads them from its row with one
+// 32-byte load; step s of the chunk uses element s.  Each wave loads its own
+// row tiles and both column tiles (the latter shared through the caches), and
+// the next chunk is loaded while the current one is multiplied.
+struct d4pack {
+    d4v a[kRT2];
+    d4v b[2];
+};
+
+__device__ __forceinline__ d4v load4(const double* __restrict__ p) {
+    return *reinterpret_cast<const d4v*>(p);
+}
+
 __device__ void update_block_column(double* __restrict__ A, int np, int J, int R,
                                     SetupLds2& s) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i16 = lane & 15, g = lane >> 4;
     const int nrow = np - R < kRows2 ? np - R : kRows2;   // multiple of 32
     const int ntile = nrow / 16;
     d4v acc[kRT2][2];
 #pragma unroll
     for (int t = 0; t < kRT2; ++t) acc[t][0] = acc[t][1] = d4v{0.0, 0.0, 0.0, 0.0};
-    const int nchunk = J / kKC2;   // J is a multiple of 32
-    constexpr int kBL = kNB * kKC2 / kT2;   // B-panel values per thread
-    static_assert(kNB * kKC2 % kT2 == 0 && kBL >= 1, "B panel must split evenly");
-    double ra[kRPT][kKC2], rb[kBL];
-    auto load = [&](int chunk) {
-        const int K = chunk * kKC2;
+    // row pointers (offset by this lane's k group)
+    const double* arow[kRT2];
 #pragma unroll
-        for (int h = 0; h < kRPT; ++h) {
-            const int r = tid + kT2 * h;
-            if (r < nrow) {
-                const double* src = A + (size_t)(R + r) * np + K;
+    for (int t = 0; t < kRT2; ++t) {
+        const int tile = wave + kW2 * t;
+        const int row = R + 16 * (tile < ntile ? tile : 0) + i16;
+        arow[t] = A + (size_t)row * np + 4 * g;
+    }
+    const double* brow0 = A + (size_t)(J + i16) * np + 4 * g;
+    const double* brow1 = A + (size_t)(J + 16 + i16) * np + 4 * g;
+    d4pack cur, nxt;
+    auto load = [&](d4pack& d, int K) {
 #pragma unroll
-                for (int q = 0; q < kKC2; ++q) ra[h][q] = src[q];
-            }
-        }
-#pragma unroll
-        for (int h = 0; h < kBL; ++h) {
-            const int idx = tid + kT2 * h;   // 32 rows x kKC2 k
-            rb[h] = A[(size_t)(J + idx / kKC2) * np + K + idx % kKC2];
-        }
+        for (int t = 0; t < kRT2; ++t)
+            if (wave + kW2 * t < ntile) d.a[t] = load4(arow[t] + K);
+        d.b[0] = load4(brow0 + K);
+        d.b[1] = load4(brow1 + K);
     };
-    auto store = [&]() {
-#pragma unroll
-        for (int h = 0; h < kRPT; ++h) {
-            const int r = tid + kT2 * h;
-#pragma unroll
-            for (int q = 0; q < kKC2; ++q) s.u.g.P[q][r] = r < nrow ? ra[h][q] : 0.0;
-        }
-#pragma unroll
-        for (int h = 0; h < kBL; ++h) {
-            const int idx = tid + kT2 * h;
-            s.u.g.Pb[idx % kKC2][idx / kKC2] = rb[h];
-        }
-    };
-    load(0);
-    __syncthreads();
-    store();
-    __syncthreads();
+    const int nchunk = J / 16;   // J is a multiple of 32
+    load(cur, 0);
     for (int ch = 0; ch < nchunk; ++ch) {
-        if (ch + 1 < nchunk) load(ch + 1);
+        if (ch + 1 < nchunk) load(nxt, 16 * (ch + 1));
 #pragma unroll
-        for (int ks = 0; ks < kKC2 / 4; ++ks) {
-            const int kr = 4 * ks + (lane >> 4);
-            const double b0 = s.u.g.Pb[kr][lane & 15];
-            const double b1 = s.u.g.Pb[kr][16 + (lane & 15)];
+        for (int st = 0; st < 4; ++st) {
 #pragma unroll
             for (int t = 0; t < kRT2; ++t) {
-                const int tile = wave + kW2 * t;
-                if (tile < ntile) {
-                    const double a = s.u.g.P[kr][16 * tile + (lane & 15)];
-                    acc[t][0] = mfma_f64(a, b0, acc[t][0]);
-                    acc[t][1] = mfma_f64(a, b1, acc[t][1]);
+                if (wave + kW2 * t < ntile) {
+                    acc[t][0] = mfma_f64(cur.a[t][st], cur.b[0][st], acc[t][0]);
+                    acc[t][1] = mfma_f64(cur.a[t][st], cur.b[1][st], acc[t][1]);
                 }
             }
         }
-        __syncthreads();
-        if (ch + 1 < nchunk) {
-            store();
-            __syncthreads();
-        }
+        cur = nxt;
     }
 #pragma unroll
     for (int t = 0; t < kRT2; ++t) {
@@ -551,8 +540,8 @@ __device__ void update_block_column(double* __restrict__ A, int np, int J, int R
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int rl = 16 * tile + (lane >> 4) + 4 * v;
-                    const int col = 16 * cb + (lane & 15);
+                    const int rl = 16 * tile + g + 4 * v;
+                    const int col = 16 * cb + i16;
                     double* ad = A + (size_t)(R + rl) * np + J + col;
                     const double nv = *ad - acc[t][cb][v];
                     *ad = nv;
