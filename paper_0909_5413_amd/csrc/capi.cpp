@@ -96,7 +96,7 @@ struct rbf_problem {
     std::vector<int> n_omega, n_c;     // per cell
     std::vector<long long> zoff_host;
     long long* zoff = nullptr;
-    int np_max = 0;
+    int np_max = 0, nc_max = 0;
     double* Z64 = nullptr;
     float* Z32 = nullptr;
     double t_pcsetup64 = 0, t_pcsetup32 = 0;
@@ -180,6 +180,7 @@ struct rbf_problem {
         a.norm = 1.0 / (2.0 * kPi * sigma * sigma);
         a.zoff = zoff;
         a.np_max = np_max;
+        a.nc_max = nc_max;
         a.ncells = ncells;
         return a;
     }
@@ -294,6 +295,7 @@ rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals,
         p->n_c[c] = own;
         p->n_omega[c] = (int)std::min<long long>(tot, 1 << 30);
         if (own > 0) maxo = std::max(maxo, p->n_omega[c]);
+        p->nc_max = std::max(p->nc_max, own);
     }
     p->np_max = (maxo + 31) / 32 * 32;
 
@@ -377,32 +379,42 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     RBF_TRY(p->alloc_n(&Z, ztot));
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
-    long long slot_elems = (long long)p->np_max * p->np_max;
-    // cells per batch (FP64: one scratch matrix per cell of a batch of three
-    // kernels; FP32: resident workgroups of the persistent kernel)
-    const long long per_cu = is64 ? 4 : 2;
-    long long nslots = std::min<long long>(nc, per_cu * cus);
-    const long long max_scratch = 4LL << 30;
+    const long long slot_elems =
+        is64 ? rbf::slot_elems64(p->np_max) : (long long)p->np_max * p->np_max;
+    // cells per batch (FP64: one scratch matrix per cell of a batch that the
+    // lockstep launches advance together; FP32: resident workgroups of the
+    // persistent kernel)
+    long long nslots = is64 ? std::min<long long>(nc, 8192) : std::min<long long>(nc, 2LL * cus);
+    const long long max_scratch = 12LL << 30;
     while (nslots > cus && nslots * slot_elems * (long long)sizeof(T) > max_scratch) nslots /= 2;
+    if (nslots > 8) nslots &= ~7LL;
     if (nslots < 1) nslots = 1;
+    const long long pad = (nslots + 7) / 8 * 8;
     T* scratch;
-    int* status;
+    int* status = nullptr;
+    int4* meta = nullptr;
+    double* lt = nullptr;
     rbf_status s = p->alloc_n(&scratch, nslots * slot_elems);
     if (s != RBF_OK) {
         p->release(Z);
         return s;
     }
     s = p->alloc_n(&status, nc);
+    if (s == RBF_OK && is64) s = p->alloc_n(&meta, pad);
+    if (s == RBF_OK && is64) s = p->alloc_n(&lt, 2 * pad * 1024);
     if (s != RBF_OK) {
         p->release(Z);
         p->release(scratch);
+        if (status) p->release(status);
+        if (meta) p->release(meta);
         return s;
     }
     rbf::PrecondArgs a = p->pc_args();
     hipError_t e;
     if (is64)
         e = rbf::launch_precond_setup64(a, reinterpret_cast<double*>(Z),
-                                        reinterpret_cast<double*>(scratch), (int)nslots, status, st);
+                                        reinterpret_cast<double*>(scratch), (int)nslots, meta,
+                                        lt, status, st);
     else
         e = rbf::launch_precond_setup32(a, reinterpret_cast<float*>(Z),
                                         reinterpret_cast<float*>(scratch), (int)nslots, status, st);
@@ -412,6 +424,8 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     p->release(scratch);
     p->release(status);
+    if (meta) p->release(meta);
+    if (lt) p->release(lt);
     if (e != hipSuccess) {
         p->release(Z);
         return fail(RBF_EDEVICE, "preconditioner setup: %s", hipGetErrorString(e));

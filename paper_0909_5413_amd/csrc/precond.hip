@@ -415,51 +415,69 @@ __global__ __launch_bounds__(kThreads) void k_precond_setup(PrecondArgs a, T* __
 }
 
 // ===========================================================================
-// FP64 setup on the matrix cores.  Two 256-thread workgroups per CU, each
-// holding one cell's matrix at a time (n_p x n_p, lower triangle, ROW-major:
-// element (i, j) at A[i * n_p + j], so every row segment is contiguous) in a
-// private global scratch; the two workgroups hide each other's memory stalls.
-// The block-column update of the left-looking Cholesky and the substitution
-// products of the inverse rows run as v_mfma_f64_16x16x4f64 tiles fed from LDS
-// panels, the next panel being loaded into registers while the current one is
-// multiplied.  Operand layout of that instruction on gfx950: lane l holds
-// A[l%16][l/16] and B[l/16][l%16]; the four result registers v hold
-// D[l/16 + 4v][l%16].
+// FP64 setup on the matrix cores, batched in lockstep.  Each cell of a batch
+// (a slot) keeps its n_p x n_p lower triangle in a scratch slot, stored by
+// block rows (see roff).  The left-looking blocked Cholesky advances one
+// 32-column block column J at a time for every slot together, one launch per
+// J: each workgroup takes a 256-row tile below the diagonal block, updates it
+// with the finished block columns as MFMA tiles (the result lands in LDS),
+// solves x L_JJ^T = a for its rows by substitution (one row per thread, L_JJ
+// broadcast from LDS), and writes the rows back.  The
+// workgroup of the first tile then also forms and factors the next diagonal
+// block, which only needs rows it has just finished.  The centre rows of the
+// inverse follow: one launch for the forward solve on the trailing rows, one
+// launch per block row of the back solve.  Every launch carries thousands of
+// independent workgroups, so one cell's serial steps overlap with other
+// cells' work.  Workgroup b serves slot b % nslots_pad (a multiple of 8): a
+// slot's workgroups run on one XCD in every launch, and its rows stay in that
+// XCD's L2 from launch to launch.
+// Operand layout of v_mfma_f64_16x16x4f64 on gfx950: lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; result register v holds D[l/16 + 4v][l%16].
 // ===========================================================================
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 
-constexpr int kT2 = 256;        // threads (4 waves)
+constexpr int kT2 = 256;        // threads of the assembly and inverse-row kernels (4 waves)
 constexpr int kW2 = kT2 / 64;
-constexpr int kKC2 = 8;         // k per LDS panel in the update
-constexpr int kRows2 = 256;     // rows per super-block of the update
-constexpr int kRT2 = kRows2 / 16 / kW2;   // row tiles per wave (8)
-constexpr int kRPT = kRows2 / kT2;        // panel rows loaded per thread (2)
-static_assert(kRows2 % kT2 == 0, "row super-block must split evenly");
+constexpr int kTS = 256;        // threads of a factorisation step (4 waves)
+constexpr int kWS = kTS / 64;
+constexpr int kRows2 = 256;     // rows per step tile
+constexpr int kRT2 = kRows2 / 16 / kWS;   // row tiles per wave (4)
+static_assert(kRows2 == kTS, "the substitution gives one row to each thread");
+constexpr int kXS = kRows2 + 1; // padded LDS row of a staged tile (conflict-free MFMA stores)
+constexpr int kTri = kNB * (kNB + 1) / 2;
+
+// Index of (k, j), j >= k, in the packed upper triangle of a 32x32 block.
+__host__ __device__ constexpr int tri(int k, int j) { return kNB * k - k * (k - 1) / 2 + (j - k); }
 constexpr int kZK = 64;         // k per LDS panel in the inverse-row products
 
-struct SetupLds2 {
+// Block-row storage of a slot's lower triangle: the 32 rows of block row I are
+// stored with stride 32 (I + 1) (their columns up to the end of the diagonal
+// block), block rows one after another, so every row starts on a 256-byte
+// boundary and a slot needs 512 B (B + 1) doubles for B block rows.
+__device__ __forceinline__ size_t roff(int row) {
+    const int I = row >> 5;
+    return (size_t)(32 * (I + 1)) * (size_t)(16 * I + (row & 31));
+}
+
+struct StepLds {
     union {
+        double X[kNB][kXS];               // the tile's rows, one column per thread
         struct {
-            double P[kKC2][kRows2];      // rows of the panel, k-major
-            double Pb[kKC2][kNB];        // the block column's own rows
-        } g;
-        struct {
-            double X[kNB][kT2];          // rows being solved, one column per thread
-        } t;
-        struct {
-            double Lc[kZK][kNB + 1];
-            double Xc[kZK][kZCols + 1];
-            double acc[kNB][kZCols + 1];
-        } z;
-        struct {
-            double mx[RBF_MAX_BLOCK];
-            double my[RBF_MAX_BLOCK];
-        } coords;
+            double D[kNB][kNB + 1];       // the next diagonal block
+            double part[kWS][3][16][17];  // per-wave partial products of its tiles
+        } d;
     } u;
+    double Lt[kTri];                      // L_JJ transposed (packed), reciprocal pivots on the diagonal
+    int flag;
+};
+
+struct ZLds {
+    double Lc[kZK][kNB + 1];
+    double Xc[kZK][kZCols + 1];
+    double acc[kNB][kZCols + 1];
     double D[kNB][kNB + 1];
     double invd[kNB];
-    int rb[kMaxRanges], re[kMaxRanges];
-    int nranges, n_omega, n_c, flag;
 };
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
@@ -468,203 +486,276 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
+
+
 __device__ __forceinline__ d4v mfma_f64(double a, double b, d4v c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-
-// A[rows R.., cols J..J+31] -= L[rows, 0:J] L[J..J+31, 0:J]^T for one row
-// super-block (MFMA tiles; J > 0).  The tiles of rows J..J+31 also go to s.D.
-// No LDS and no barriers: the contraction index of an MFMA may be permuted as
-// long as A and B use the same permutation, so over a chunk of 16 k values lane
-// group g = l/16 owns k = K+4g .. K+4g+3 and loads them from its row with one
-// 32-byte load; step s of the chunk uses element s.  Each wave loads its own
-// row tiles and both column tiles (the latter shared through the caches), and
-// the next chunk is loaded while the current one is multiplied.
-struct d4pack {
-    d4v a[kRT2];
-    d4v b[2];
-};
 
 __device__ __forceinline__ d4v load4(const double* __restrict__ p) {
     return *reinterpret_cast<const d4v*>(p);
 }
 
-__device__ void update_block_column(double* __restrict__ A, int np, int J, int R,
-                                    SetupLds2& s) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i16 = lane & 15, g = lane >> 4;
-    const int nrow = np - R < kRows2 ? np - R : kRows2;   // multiple of 32
-    const int ntile = nrow / 16;
-    d4v acc[kRT2][2];
+// X[c][r] = A[R + r][J + c] - sum_{k < J} L[R + r][k] L[J + c][k] for the
+// nrow (a multiple of 32, <= 256) rows of the tile, J > 0.  MFMA tiles with
+// no LDS staging and no barriers: the contraction index of an MFMA may be
+// permuted as long as A and B use the same permutation, so over a chunk of 16
+// k values lane group g = l/16 owns k = K+4g .. K+4g+3 and loads them from its
+// row with one 32-byte load; step s of the chunk uses element s.  Each wave
+// loads its own M row tiles (three register buffers: two chunks in flight
+// while one is multiplied) and both column tiles (shared by the waves through
+// the caches; two buffers).  Six chunks per loop pass keep every buffer index
+// a constant and the body free of branches, so each multiply waits only for
+// its own loads.
+template <int M>
+struct UpdateRegs {
+    d4v a[3][M];
+    d4v b[2][2];
+    d4v acc[M][2];
+    const double* arow[M];
+    const double* brow[2];
+
+    __device__ __forceinline__ void load_a(int buf, int ch) {
 #pragma unroll
-    for (int t = 0; t < kRT2; ++t) acc[t][0] = acc[t][1] = d4v{0.0, 0.0, 0.0, 0.0};
-    // row pointers (offset by this lane's k group)
-    const double* arow[kRT2];
-#pragma unroll
-    for (int t = 0; t < kRT2; ++t) {
-        const int tile = wave + kW2 * t;
-        const int row = R + 16 * (tile < ntile ? tile : 0) + i16;
-        arow[t] = A + (size_t)row * np + 4 * g;
+        for (int t = 0; t < M; ++t) a[buf][t] = load4(arow[t] + 16 * ch);
     }
-    const double* brow0 = A + (size_t)(J + i16) * np + 4 * g;
-    const double* brow1 = A + (size_t)(J + 16 + i16) * np + 4 * g;
-    d4pack cur, nxt;
-    auto load = [&](d4pack& d, int K) {
-#pragma unroll
-        for (int t = 0; t < kRT2; ++t)
-            if (wave + kW2 * t < ntile) d.a[t] = load4(arow[t] + K);
-        d.b[0] = load4(brow0 + K);
-        d.b[1] = load4(brow1 + K);
-    };
-    const int nchunk = J / 16;   // J is a multiple of 32
-    load(cur, 0);
-    for (int ch = 0; ch < nchunk; ++ch) {
-        if (ch + 1 < nchunk) load(nxt, 16 * (ch + 1));
+    __device__ __forceinline__ void load_b(int buf, int ch) {
+        b[buf][0] = load4(brow[0] + 16 * ch);
+        b[buf][1] = load4(brow[1] + 16 * ch);
+    }
+    __device__ __forceinline__ void mma(int ba, int bb) {
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
 #pragma unroll
-            for (int t = 0; t < kRT2; ++t) {
-                if (wave + kW2 * t < ntile) {
-                    acc[t][0] = mfma_f64(cur.a[t][st], cur.b[0][st], acc[t][0]);
-                    acc[t][1] = mfma_f64(cur.a[t][st], cur.b[1][st], acc[t][1]);
-                }
+            for (int t = 0; t < M; ++t) {
+                acc[t][0] = mfma_f64(a[ba][t][st], b[bb][0][st], acc[t][0]);
+                acc[t][1] = mfma_f64(a[ba][t][st], b[bb][1][st], acc[t][1]);
             }
         }
-        cur = nxt;
     }
+    // chunks c .. c + min(R, 6) - 1; on entry chunks c, c + 1 of A and chunk c
+    // of B are loaded (c is a multiple of 6), no load reaches c + R
+    template <int R>
+    __device__ __forceinline__ void run(int c) {
 #pragma unroll
-    for (int t = 0; t < kRT2; ++t) {
-        const int tile = wave + kW2 * t;
-        if (tile < ntile) {
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int rl = 16 * tile + g + 4 * v;
-                    const int col = 16 * cb + i16;
-                    double* ad = A + (size_t)(R + rl) * np + J + col;
-                    const double nv = *ad - acc[t][cb][v];
-                    *ad = nv;
-                    if (R == J && rl < kNB) s.D[rl][col] = nv;
-                }
+        for (int i = 0; i < 6; ++i) {
+            if (i < R) {
+                if (i + 2 < R) load_a((i + 2) % 3, c + i + 2);
+                if (i + 1 < R) load_b((i + 1) % 2, c + i + 1);
+                mma(i % 3, i % 2);
+            }
         }
+    }
+};
+
+template <int M>
+__device__ __forceinline__ void update_core(const double* __restrict__ A, int J, int R, int wave,
+                                            double (*X)[kXS]) {
+    const int lane = threadIdx.x & 63;
+    const int i16 = lane & 15, g = lane >> 4;
+    UpdateRegs<M> u;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        u.acc[t][0] = u.acc[t][1] = d4v{0.0, 0.0, 0.0, 0.0};
+        u.arow[t] = A + roff(R + 16 * (wave + kWS * t) + i16) + 4 * g;
+    }
+    u.brow[0] = A + roff(J + i16) + 4 * g;
+    u.brow[1] = A + roff(J + 16 + i16) + 4 * g;
+    const int nchunk = J / 16;   // >= 2, even
+    u.load_a(0, 0);
+    u.load_a(1, 1);
+    u.load_b(0, 0);
+    int c = 0;
+    for (; c + 8 <= nchunk; c += 6) u.template run<99>(c);
+    const int rest = nchunk - c;   // 2, 4 or 6
+    if (rest == 2)
+        u.template run<2>(c);
+    else if (rest == 4)
+        u.template run<4>(c);
+    else
+        u.template run<6>(c);
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const int tile = wave + kWS * t;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rl = 16 * tile + g + 4 * v;
+                const int col = 16 * cb + i16;
+                X[col][rl] = A[roff(R + rl) + J + col] - u.acc[t][cb][v];
+            }
     }
 }
 
-// Factor the 32x32 diagonal block (in s.D) in wave 0's registers (lane i holds
-// row i; broadcasts by readlane, no barriers), write it back and keep it in
-// s.D / s.invd.  Returns 0 or the failing 1-based pivot index (all threads).
-__device__ int factor_diag_block(double* __restrict__ A, int np, int J, SetupLds2& s) {
+__device__ void update_tile(const double* __restrict__ A, int J, int R, int nrow,
+                            double (*X)[kXS]) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntile = nrow / 16;
+    const int mine = (ntile - wave + kWS - 1) / kWS;   // row tiles of this wave (uniform)
+    static_assert(kRT2 == 4, "row tiles per wave");
+    switch (mine) {
+        case 4: update_core<4>(A, J, R, wave, X); break;
+        case 3: update_core<3>(A, J, R, wave, X); break;
+        case 2: update_core<2>(A, J, R, wave, X); break;
+        case 1: update_core<1>(A, J, R, wave, X); break;
+        default: break;
+    }
+}
+
+// X[c][r] = A[R + r][J + c] (coalesced 16-byte loads), r < nrow.
+__device__ void load_tile(const double* __restrict__ A, int J, int R, int nrow, double (*X)[kXS]) {
+    for (int id = threadIdx.x; id < nrow * (kNB / 2); id += kTS) {
+        const int r = id / (kNB / 2), c = 2 * (id % (kNB / 2));
+        const d2v v = *reinterpret_cast<const d2v*>(A + roff(R + r) + J + c);
+        X[c][r] = v[0];
+        X[c + 1][r] = v[1];
+    }
+}
+
+// A[R + r][J + c] = X[c][r] (coalesced 16-byte stores), r < nrow.
+__device__ void store_tile(double* __restrict__ A, int J, int R, int nrow, double (*X)[kXS]) {
+    for (int id = threadIdx.x; id < nrow * (kNB / 2); id += kTS) {
+        const int r = id / (kNB / 2), c = 2 * (id % (kNB / 2));
+        d2v v;
+        v[0] = X[c][r];
+        v[1] = X[c + 1][r];
+        *reinterpret_cast<d2v*>(A + roff(R + r) + J + c) = v;
+    }
+}
+
+// Row tid of the tile: x L_JJ^T = a in place (column tid of X), column by
+// column so that every step is 31 - k independent FMAs.  Lt holds L_JJ
+// transposed (Lt[k][j] = L[j][k], j > k) with the reciprocal pivots on its
+// diagonal; every lane reads the same Lt entries (LDS broadcasts).
+__device__ __forceinline__ void trsm_tile(const double* Lt, int nrow, double (*X)[kXS]) {
+    const int tid = threadIdx.x;
+    if (tid >= nrow) return;
+    double x[kNB];
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) x[q] = X[q][tid];
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) {
+        x[k] *= Lt[tri(k, k)];
+#pragma unroll
+        for (int j = k + 1; j < kNB; ++j) x[j] = __builtin_fma(-x[k], Lt[tri(k, j)], x[j]);
+    }
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) X[q][tid] = x[q];
+}
+
+// D = A[J0.., J0..] - L[J0.., 0:J0] L[J0.., 0:J0]^T on the three lower 16x16
+// tiles of the 32x32 diagonal block, J0 > 0: wave w multiplies all three
+// tiles over its quarter of the chunks (three independent MFMA chains), and
+// the four partial products are summed through LDS.
+__device__ __forceinline__ void syrk_diag(const double* __restrict__ A, int J0,
+                                          double (*D)[kNB + 1], double (*part)[3][16][17]) {
+    static_assert(kWS == 4, "four partial products");
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i16 = lane & 15, g = lane >> 4;
+    const double* r0 = A + roff(J0 + i16) + 4 * g;        // rows J0 .. J0+15
+    const double* r1 = A + roff(J0 + 16 + i16) + 4 * g;   // rows J0+16 .. J0+31
+    d4v t00 = {0.0, 0.0, 0.0, 0.0}, t10 = t00, t11 = t00;
+    auto mma = [&](const d4v& a0, const d4v& a1) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            t00 = mfma_f64(a0[st], a0[st], t00);
+            t10 = mfma_f64(a1[st], a0[st], t10);
+            t11 = mfma_f64(a1[st], a1[st], t11);
+        }
+    };
+    // chunks wave, wave + 4, ...: two register buffers in turn
+    const int nchunk = J0 / 16;
+    d4v p0 = {0.0, 0.0, 0.0, 0.0}, p1 = p0, q0 = p0, q1 = p0;
+    if (wave < nchunk) {
+        p0 = load4(r0 + 16 * wave);
+        p1 = load4(r1 + 16 * wave);
+    }
+    for (int ch = wave; ch < nchunk; ch += 2 * kWS) {
+        const bool second = ch + kWS < nchunk;
+        if (second) {
+            q0 = load4(r0 + 16 * (ch + kWS));
+            q1 = load4(r1 + 16 * (ch + kWS));
+        }
+        mma(p0, p1);
+        if (ch + 2 * kWS < nchunk) {
+            p0 = load4(r0 + 16 * (ch + 2 * kWS));
+            p1 = load4(r1 + 16 * (ch + 2 * kWS));
+        }
+        if (second) mma(q0, q1);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = g + 4 * v;
+        part[wave][0][r][i16] = t00[v];
+        part[wave][1][r][i16] = t10[v];
+        part[wave][2][r][i16] = t11[v];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 3 * 256; idx += kTS) {
+        const int t = idx >> 8, r = (idx >> 4) & 15, c = idx & 15;
+        const double sum = (part[0][t][r][c] + part[1][t][r][c]) + (part[2][t][r][c] + part[3][t][r][c]);
+        const int row = 16 * (t == 0 ? 0 : 1) + r, col = 16 * (t == 2 ? 1 : 0) + c;
+        D[row][col] = A[roff(J0 + row) + J0 + col] - sum;
+    }
+}
+
+// Factor the 32x32 diagonal block J0 (lower part of D) in wave 0's registers
+// (lane i holds row i; broadcasts by readlane, no barriers).  Step k: the
+// pivot, its reciprocal square root (hardware estimate and two Newton steps),
+// column k of L written to A and, transposed with the reciprocal pivot on the
+// diagonal, to Lt, then the rank-1 update of the rows below.  Returns 0 or J0
+// + the failing 1-based pivot index (all threads).
+__device__ __forceinline__ int factor_diag_block(double* __restrict__ A, int J0,
+                                                 double (*D)[kNB + 1], int* flag,
+                                                 double* __restrict__ Lt) {
     const int tid = threadIdx.x;
     if (tid < 64) {
         const int i = tid & 31;
+        const bool own = tid < kNB;
+        double* arow = A + roff(J0 + i) + J0;
         double r[kNB];
 #pragma unroll
-        for (int c = 0; c < kNB; ++c) r[c] = (c <= i) ? s.D[i][c] : 0.0;
+        for (int c = 0; c < kNB; ++c) r[c] = (c <= i) ? D[i][c] : 0.0;
         int bad = 0;
 #pragma unroll
         for (int k = 0; k < kNB; ++k) {
             const double piv = readlane_d(r[k], k);
             if (!bad && !(piv > 0.0)) bad = k + 1;   // uniform; later values are moot
-            const double lkk = __builtin_sqrt(piv);
-            const double inv = 1.0 / lkk;
-            r[k] = (i == k) ? lkk : r[k] * inv;
+            double y = __builtin_amdgcn_rsq(piv);
+            y = y * __builtin_fma(-0.5 * piv * y, y, 1.5);
+            y = y * __builtin_fma(-0.5 * piv * y, y, 1.5);
+            const double l = (i == k) ? piv * y : r[k] * y;
+            r[k] = l;
 #pragma unroll
             for (int j = k + 1; j < kNB; ++j) {
-                const double ljk = readlane_d(r[k], j);
-                r[j] = __builtin_fma(-r[k], ljk, r[j]);
+                r[j] = __builtin_fma(-l, readlane_d(l, j), r[j]);
+                // the update happens here, not where r[j] is next read: the
+                // broadcast values stay short-lived (no SGPR spills)
+                __asm__ volatile("" : "+v"(r[j]));
+            }
+            if (own && i >= k) {
+                arow[k] = l;
+                Lt[k * kNB + i] = (i == k) ? y : l;
             }
         }
-        if (tid == 0) s.flag = bad ? J + bad : 0;
-        if (!bad && tid < kNB) {
-            double* arow = A + (size_t)(J + i) * np + J;
-#pragma unroll
-            for (int c = 0; c < kNB; ++c) {
-                if (c <= i) {
-                    arow[c] = r[c];
-                    s.D[i][c] = r[c];
-                }
-            }
-            s.invd[i] = 1.0 / r[i];
-        }
+        if (tid == 0) *flag = bad ? J0 + bad : 0;
     }
     __syncthreads();
-    return s.flag;
+    return *flag;
 }
 
-// Rows J+32 .. np-1 of block column J: x L_JJ^T = a, one row per thread, the
-// row staged in LDS (column tid of s.u.t.X) and solved in 4 groups of 8.
-__device__ void trsm_rows(double* __restrict__ A, int np, int J, SetupLds2& s) {
-    const int tid = threadIdx.x;
-    for (int r0 = J + kNB; r0 < np; r0 += kT2) {
-        const int row = r0 + tid;
-        double* xr = A + (size_t)row * np + J;
-        if (row < np) {
-            double x[kNB];
-#pragma unroll
-            for (int q = 0; q < kNB; ++q) x[q] = xr[q];
-#pragma unroll
-            for (int q = 0; q < kNB; ++q) s.u.t.X[q][tid] = x[q];
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                double y[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) y[q] = s.u.t.X[8 * g + q][tid];
-#pragma unroll
-                for (int c = 0; c < 8 * g; ++c) {
-                    const double xc = s.u.t.X[c][tid];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) y[q] = __builtin_fma(-xc, s.D[8 * g + q][c], y[q]);
-                    __asm__ volatile("" ::: "memory");
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    y[q] = y[q] * s.invd[8 * g + q];
-#pragma unroll
-                    for (int q2 = q + 1; q2 < 8; ++q2)
-                        y[q2] = __builtin_fma(-y[q], s.D[8 * g + q2][8 * g + q], y[q2]);
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    s.u.t.X[8 * g + q][tid] = y[q];
-                    xr[8 * g + q] = y[q];
-                }
-                __asm__ volatile("" ::: "memory");
-            }
-        }
-    }
-}
-
-__device__ int cholesky_mfma(double* __restrict__ A, int np, SetupLds2& s) {
-    const int tid = threadIdx.x;
-    for (int J = 0; J < np; J += kNB) {
-        if (J > 0) {
-            for (int R = J; R < np; R += kRows2) update_block_column(A, np, J, R, s);
-        } else {
-            for (int idx = tid; idx < kNB * kNB; idx += kT2) {
-                const int i = idx / kNB, j = idx % kNB;
-                if (j <= i) s.D[i][j] = A[(size_t)i * np + j];
-            }
-        }
-        __syncthreads();
-        const int f = factor_diag_block(A, np, J, s);
-        if (f) return f;
-        trsm_rows(A, np, J, s);
-        __syncthreads();
-    }
-    return 0;
-}
-
-// s.u.z.acc[r][c] = rhs(r, c) - sum_k op(L)[I0 + r][k] X[k][c0 + c] over
+// s.acc[r][c] = rhs(r, c) - sum_k op(L)[I0 + r][k] X[k][c0 + c] over
 // k in [k_lo, k_hi) (MFMA, 8 tiles of 16x16, two per wave), then the diagonal
 // block L(I0.., I0..) into s.D / s.invd.
 //   forward (kBackward = false): op(L)[r][k] = L[r][k], rhs = E_C
 //   backward: op(L)[r][k] = L[k][r], rhs = the forward result W stored in X's
 //   place (zero above row w_lo)
 template <bool kBackward>
-__device__ void zsolve_block(const double* __restrict__ A, int np, int I0, int k_lo, int k_hi,
+__device__ void zsolve_block(const double* __restrict__ A, int I0, int k_lo, int k_hi,
                              const double* __restrict__ Zc, int ldz, int p, int c0, int ncol,
-                             int q0, int w_lo, SetupLds2& s) {
+                             int q0, int w_lo, ZLds& s) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rt = wave >> 1, ct0 = 2 * (wave & 1);
     d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
@@ -681,10 +772,10 @@ __device__ void zsolve_block(const double* __restrict__ A, int np, int I0, int k
             double v = 0.0;
             if (kBackward) {   // L[k0 + kk][I0 + rr]: contiguous in rr
                 const int kk = idx / kNB, rr = idx % kNB;
-                if (k0 + kk < k_hi) v = A[(size_t)(k0 + kk) * np + I0 + rr];
+                if (k0 + kk < k_hi) v = A[roff(k0 + kk) + I0 + rr];
             } else {           // L[I0 + rr][k0 + kk]: contiguous in kk
                 const int rr = idx / kZK, kk = idx % kZK;
-                if (k0 + kk < k_hi) v = A[(size_t)(I0 + rr) * np + k0 + kk];
+                if (k0 + kk < k_hi) v = A[roff(I0 + rr) + k0 + kk];
             }
             rl[q] = v;
         }
@@ -703,14 +794,14 @@ __device__ void zsolve_block(const double* __restrict__ A, int np, int I0, int k
         for (int q = 0; q < kLL; ++q) {
             const int idx = tid + kT2 * q;
             if (kBackward)
-                s.u.z.Lc[idx / kNB][idx % kNB] = rl[q];
+                s.Lc[idx / kNB][idx % kNB] = rl[q];
             else
-                s.u.z.Lc[idx % kZK][idx / kZK] = rl[q];
+                s.Lc[idx % kZK][idx / kZK] = rl[q];
         }
 #pragma unroll
         for (int q = 0; q < kLX; ++q) {
             const int idx = tid + kT2 * q;
-            s.u.z.Xc[idx % kZK][idx / kZK] = rx[q];
+            s.Xc[idx % kZK][idx / kZK] = rx[q];
         }
     };
     __syncthreads();
@@ -723,9 +814,9 @@ __device__ void zsolve_block(const double* __restrict__ A, int np, int I0, int k
 #pragma unroll
             for (int ks = 0; ks < kZK / 4; ++ks) {
                 const int kr = 4 * ks + (lane >> 4);
-                const double a = s.u.z.Lc[kr][16 * rt + (lane & 15)];
-                const double b0 = s.u.z.Xc[kr][16 * ct0 + (lane & 15)];
-                const double b1 = s.u.z.Xc[kr][16 * ct0 + 16 + (lane & 15)];
+                const double a = s.Lc[kr][16 * rt + (lane & 15)];
+                const double b0 = s.Xc[kr][16 * ct0 + (lane & 15)];
+                const double b1 = s.Xc[kr][16 * ct0 + 16 + (lane & 15)];
                 acc0 = mfma_f64(a, b0, acc0);
                 acc1 = mfma_f64(a, b1, acc1);
             }
@@ -750,103 +841,67 @@ __device__ void zsolve_block(const double* __restrict__ A, int np, int I0, int k
                 else
                     rhs = (row == q0 + c0 + cc) ? 1.0 : 0.0;
             }
-            s.u.z.acc[r][cc] = rhs - (h ? acc1[v] : acc0[v]);
+            s.acc[r][cc] = rhs - (h ? acc1[v] : acc0[v]);
         }
     }
     for (int idx = tid; idx < kNB * kNB; idx += kT2) {
         const int i = idx / kNB, j = idx % kNB;
-        s.D[i][j] = A[(size_t)(I0 + i) * np + I0 + j];
+        s.D[i][j] = (j <= i) ? A[roff(I0 + i) + I0 + j] : 0.0;
     }
     __syncthreads();
     if (tid < kNB) s.invd[tid] = 1.0 / s.D[tid][tid];
     __syncthreads();
 }
 
-__device__ void centre_rows_mfma(const double* __restrict__ A, int np, int p, int n_omega,
-                                 int n_c, double* __restrict__ Zc, SetupLds2& s) {
-    const int tid = threadIdx.x;
-    const int q0 = np - n_c;
-    const int ib = q0 / kNB;
-    const int nblk = np / kNB;
-    for (int c0 = 0; c0 < n_c; c0 += kZCols) {
-        const int ncol = n_c - c0 < kZCols ? n_c - c0 : kZCols;
-        for (int I = ib; I < nblk; ++I) {
-            const int I0 = I * kNB;
-            zsolve_block<false>(A, np, I0, ib * kNB, I0, Zc, n_omega, p, c0, ncol, q0, 0, s);
-            if (tid < ncol) {
-                for (int r = 0; r < kNB; ++r) {
-                    double v = s.u.z.acc[r][tid];
-                    for (int r2 = 0; r2 < r; ++r2)
-                        v = __builtin_fma(-s.D[r][r2], s.u.z.acc[r2][tid], v);
-                    s.u.z.acc[r][tid] = v * s.invd[r];
-                }
-                for (int r = 0; r < kNB; ++r)
-                    if (I0 + r >= p) Zc[(size_t)(c0 + tid) * n_omega + (I0 + r - p)] = s.u.z.acc[r][tid];
-            }
-        }
-        for (int I = nblk - 1; I >= 0; --I) {
-            const int I0 = I * kNB;
-            if (I0 + kNB <= p) break;
-            zsolve_block<true>(A, np, I0, I0 + kNB, np, Zc, n_omega, p, c0, ncol, q0, ib * kNB, s);
-            if (tid < ncol) {
-                for (int r = kNB - 1; r >= 0; --r) {
-                    double v = s.u.z.acc[r][tid];
-                    for (int r2 = r + 1; r2 < kNB; ++r2)
-                        v = __builtin_fma(-s.D[r2][r], s.u.z.acc[r2][tid], v);
-                    s.u.z.acc[r][tid] = v * s.invd[r];
-                }
-                for (int r = 0; r < kNB; ++r)
-                    if (I0 + r >= p) Zc[(size_t)(c0 + tid) * n_omega + (I0 + r - p)] = s.u.z.acc[r][tid];
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// The FP64 setup runs as three kernels over a batch of cells, one workgroup per
-// cell and a private scratch matrix per workgroup, so that each phase gets its
-// own register allocation: assemble the local matrix, factor it, form the
-// centre rows of its inverse.  Cell of workgroup b: c0 + b.
-
+// Per-slot record kept in device memory for the launches of one batch:
+// x = n_p, y = n_omega, z = n_c, w = 1 while the slot's cell is being built
+// (0: empty cell, beyond the last cell, or a failed pivot).
 struct AssembleLds {
     double mx[RBF_MAX_BLOCK];
     double my[RBF_MAX_BLOCK];
+    double D[kNB][kNB + 1];
     int rb[kMaxRanges], re[kMaxRanges];
     int nranges, n_omega, n_c, flag;
 };
 
-template <typename S>
-__device__ __forceinline__ bool load_cell_ranges(const PrecondArgs& a, long long c, S& s) {
-    if (threadIdx.x == 0) {
-        block_ranges(a.cell_start, a.g, a.overlap, c, s.rb, s.re, &s.nranges, &s.n_omega,
-                     &s.n_c);
-        s.flag = 0;
-    }
-    __syncthreads();
-    return s.n_c > 0;
-}
-
+// Slot b: members of cell c0 + b, the untruncated Gaussian on them (lower
+// triangle, leading identity padding), the slot record, status 0, and the
+// factor of the first diagonal block.
 __global__ __launch_bounds__(kT2, 2) void k_setup_assemble_f64(PrecondArgs a, long long c0,
-                                                               double* __restrict__ scratch) {
+                                                               int nslots,
+                                                               double* __restrict__ scratch,
+                                                               int4* __restrict__ meta,
+                                                               int* __restrict__ status,
+                                                               double* __restrict__ lt_out) {
     __shared__ AssembleLds s;
-    const long long c = c0 + blockIdx.x;
-    if (c >= a.ncells) return;
+    const int slot = blockIdx.x;
+    const long long c = c0 + slot;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (!load_cell_ranges(a, c, s)) return;
-    const int n_omega = s.n_omega, nr = s.nranges;
+    if (slot >= nslots || c >= a.ncells) {
+        if (tid == 0) meta[slot] = int4{0, 0, 0, 0};
+        return;
+    }
+    if (tid == 0)
+        block_ranges(a.cell_start, a.g, a.overlap, c, s.rb, s.re, &s.nranges, &s.n_omega, &s.n_c);
+    __syncthreads();
+    const int n_omega = s.n_omega, n_c = s.n_c, nr = s.nranges;
     const int np = (n_omega + kNB - 1) / kNB * kNB;
+    if (tid == 0) {
+        meta[slot] = int4{np, n_omega, n_c, n_c > 0 ? 1 : 0};
+        status[c] = 0;
+    }
+    if (n_c == 0) return;
     const int p = np - n_omega;
-    double* A = scratch + (size_t)blockIdx.x * a.np_max * a.np_max;
+    double* A = scratch + (size_t)slot * slot_elems64(a.np_max);
     for (int k = tid; k < n_omega; k += kT2) {
         const int m = member_index(s.rb, s.re, nr, k);
         s.mx[k] = a.xs[m];
         s.my[k] = a.ys[m];
     }
     __syncthreads();
-    // untruncated Gaussian, lower triangle (row-major), leading identity
-    // padding; wave w fills rows w, w + 4, ...
+    // wave w fills rows w, w + 4, ...; the first 32 rows also go to D
     for (int i = wave; i < np; i += kW2) {
-        double* arow = A + (size_t)i * np;
+        double* arow = A + roff(i);
         for (int j = lane; j <= i; j += 64) {
             double v;
             if (i < p || j < p) {
@@ -857,38 +912,124 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble_f64(PrecondArgs a, lo
                 v = exp_neg(__builtin_fma(dx, dx, dy * dy) * a.mk) * a.norm;
             }
             arow[j] = v;
+            if (i < kNB) s.D[i][j] = v;
+        }
+    }
+    __syncthreads();
+    const int f = factor_diag_block(A, 0, s.D, &s.flag, lt_out + (size_t)slot * kNB * kNB);
+    if (f && tid == 0) {
+        status[c] = f;
+        meta[slot].w = 0;
+    }
+}
+
+// Block column J: workgroup b takes the 256-row tile b / nslots_pad below the
+// diagonal block of slot b % nslots_pad; the first tile's workgroup then
+// factors diagonal block J + 32.  lt_in / lt_out: per slot, L_JJ and L_{J+32}
+// transposed with reciprocal pivots (two buffers, alternating with J).
+__global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, long long c0, int J,
+                                                      int nslots_pad, double* __restrict__ scratch,
+                                                      int4* __restrict__ meta,
+                                                      int* __restrict__ status,
+                                                      const double* __restrict__ lt_in,
+                                                      double* __restrict__ lt_out) {
+    __shared__ StepLds s;
+    const int slot = blockIdx.x % nslots_pad, tile = blockIdx.x / nslots_pad;
+    const int4 m = meta[slot];
+    const int np = m.x;
+    const int R = J + kNB + kRows2 * tile;
+    if (!m.w || R >= np) return;
+    const int tid = threadIdx.x;
+    double* A = scratch + (size_t)slot * slot_elems64(a.np_max);
+    const int nrow = np - R < kRows2 ? np - R : kRows2;
+    for (int e = tid; e < kNB * kNB; e += kTS) {
+        const int k = e / kNB, j = e % kNB;
+        if (j >= k) s.Lt[tri(k, j)] = lt_in[(size_t)slot * kNB * kNB + e];
+    }
+    if (J > 0)
+        update_tile(A, J, R, nrow, s.u.X);
+    else
+        load_tile(A, J, R, nrow, s.u.X);
+    __syncthreads();
+    trsm_tile(s.Lt, nrow, s.u.X);
+    __syncthreads();
+    store_tile(A, J, R, nrow, s.u.X);
+    if (tile == 0) {
+        __syncthreads();
+        syrk_diag(A, J + kNB, s.u.d.D, s.u.d.part);
+        __syncthreads();
+        const int f = factor_diag_block(A, J + kNB, s.u.d.D, &s.flag,
+                                        lt_out + (size_t)slot * kNB * kNB);
+        if (f && tid == 0) {
+            status[c0 + slot] = f;
+            meta[slot].w = 0;
         }
     }
 }
 
-__global__ __launch_bounds__(kT2, 2) void k_setup_factor_f64(PrecondArgs a, long long c0,
-                                                             double* __restrict__ scratch,
-                                                             int* __restrict__ status) {
-    __shared__ SetupLds2 s;
-    const long long c = c0 + blockIdx.x;
-    if (c >= a.ncells) return;
-    if (!load_cell_ranges(a, c, s)) {
-        if (threadIdx.x == 0) status[c] = 0;
-        return;
+// Centre rows, forward part: L W = E_C on the trailing block rows; workgroup
+// b takes the 64 right-hand sides (b / nslots_pad) of slot b % nslots_pad.
+// X(k, col) lives at Zc[col * n_omega + k - p] (padding rows are zero).
+__global__ __launch_bounds__(kT2, 2) void k_z_forward(PrecondArgs a, long long c0, int nslots_pad,
+                                                      const double* __restrict__ scratch,
+                                                      const int4* __restrict__ meta,
+                                                      double* __restrict__ Z) {
+    __shared__ ZLds s;
+    const int slot = blockIdx.x % nslots_pad, cp = blockIdx.x / nslots_pad;
+    const int4 m = meta[slot];
+    const int np = m.x, n_omega = m.y, n_c = m.z;
+    const int col0 = cp * kZCols;
+    if (!m.w || col0 >= n_c) return;
+    const int tid = threadIdx.x;
+    const int ncol = n_c - col0 < kZCols ? n_c - col0 : kZCols;
+    const int p = np - n_omega, q0 = np - n_c, ib = q0 / kNB, nblk = np / kNB;
+    const double* A = scratch + (size_t)slot * slot_elems64(a.np_max);
+    double* Zc = Z + a.zoff[c0 + slot];
+    for (int I = ib; I < nblk; ++I) {
+        const int I0 = I * kNB;
+        zsolve_block<false>(A, I0, ib * kNB, I0, Zc, n_omega, p, col0, ncol, q0, 0, s);
+        if (tid < ncol) {
+            for (int r = 0; r < kNB; ++r) {
+                double v = s.acc[r][tid];
+                for (int r2 = 0; r2 < r; ++r2) v = __builtin_fma(-s.D[r][r2], s.acc[r2][tid], v);
+                s.acc[r][tid] = v * s.invd[r];
+            }
+            for (int r = 0; r < kNB; ++r)
+                if (I0 + r >= p) Zc[(size_t)(col0 + tid) * n_omega + (I0 + r - p)] = s.acc[r][tid];
+        }
     }
-    const int np = (s.n_omega + kNB - 1) / kNB * kNB;
-    double* A = scratch + (size_t)blockIdx.x * a.np_max * a.np_max;
-    const int fail = cholesky_mfma(A, np, s);
-    if (threadIdx.x == 0) status[c] = fail;
 }
 
-__global__ __launch_bounds__(kT2, 2) void k_setup_centre_rows_f64(PrecondArgs a, long long c0,
-                                                                  double* __restrict__ Z,
-                                                                  const double* __restrict__ scratch,
-                                                                  const int* __restrict__ status) {
-    __shared__ SetupLds2 s;
-    const long long c = c0 + blockIdx.x;
-    if (c >= a.ncells || status[c] != 0) return;
-    if (!load_cell_ranges(a, c, s)) return;
-    const int n_omega = s.n_omega, n_c = s.n_c;
-    const int np = (n_omega + kNB - 1) / kNB * kNB;
-    const double* A = scratch + (size_t)blockIdx.x * a.np_max * a.np_max;
-    centre_rows_mfma(A, np, np - n_omega, n_omega, n_c, Z + a.zoff[c], s);
+// Centre rows, back solve of block row I: L_II^T X_I = W_I - L[below, I]^T
+// X[below]; the slot's block rows are visited from its last one up.
+__global__ __launch_bounds__(kT2, 2) void k_z_back(PrecondArgs a, long long c0, int I,
+                                                   int nslots_pad,
+                                                   const double* __restrict__ scratch,
+                                                   const int4* __restrict__ meta,
+                                                   double* __restrict__ Z) {
+    __shared__ ZLds s;
+    const int slot = blockIdx.x % nslots_pad, cp = blockIdx.x / nslots_pad;
+    const int4 m = meta[slot];
+    const int np = m.x, n_omega = m.y, n_c = m.z;
+    const int col0 = cp * kZCols;
+    const int I0 = I * kNB;
+    const int p = np - n_omega;
+    if (!m.w || col0 >= n_c || I0 >= np || I0 + kNB <= p) return;
+    const int tid = threadIdx.x;
+    const int ncol = n_c - col0 < kZCols ? n_c - col0 : kZCols;
+    const int q0 = np - n_c, ib = q0 / kNB;
+    const double* A = scratch + (size_t)slot * slot_elems64(a.np_max);
+    double* Zc = Z + a.zoff[c0 + slot];
+    zsolve_block<true>(A, I0, I0 + kNB, np, Zc, n_omega, p, col0, ncol, q0, ib * kNB, s);
+    if (tid < ncol) {
+        for (int r = kNB - 1; r >= 0; --r) {
+            double v = s.acc[r][tid];
+            for (int r2 = r + 1; r2 < kNB; ++r2) v = __builtin_fma(-s.D[r2][r], s.acc[r2][tid], v);
+            s.acc[r][tid] = v * s.invd[r];
+        }
+        for (int r = 0; r < kNB; ++r)
+            if (I0 + r >= p) Zc[(size_t)(col0 + tid) * n_omega + (I0 + r - p)] = s.acc[r][tid];
+    }
 }
 
 template <typename T>
@@ -929,13 +1070,23 @@ __global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T*
 }  // namespace
 
 hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scratch, int nslots,
-                                  int* status, hipStream_t st) {
+                                  int4* meta, double* lt, int* status, hipStream_t st) {
+    const int pad = (nslots + 7) / 8 * 8;
+    const int ncp = (a.nc_max + kZCols - 1) / kZCols;
+    double* lt_buf[2] = {lt, lt + (size_t)pad * kNB * kNB};
     for (long long c0 = 0; c0 < a.ncells; c0 += nslots) {
-        const long long left = a.ncells - c0;
-        const unsigned grid = (unsigned)(left < nslots ? left : nslots);
-        k_setup_assemble_f64<<<grid, kT2, 0, st>>>(a, c0, scratch);
-        k_setup_factor_f64<<<grid, kT2, 0, st>>>(a, c0, scratch, status);
-        k_setup_centre_rows_f64<<<grid, kT2, 0, st>>>(a, c0, Z, scratch, status);
+        k_setup_assemble_f64<<<pad, kT2, 0, st>>>(a, c0, nslots, scratch, meta, status, lt_buf[0]);
+        for (int J = 0; J + kNB < a.np_max; J += kNB) {
+            const int tiles = (a.np_max - J - kNB + kRows2 - 1) / kRows2;
+            const int b = (J / kNB) & 1;
+            k_chol_step<<<pad * tiles, kTS, 0, st>>>(a, c0, J, pad, scratch, meta, status,
+                                                     lt_buf[b], lt_buf[b ^ 1]);
+        }
+        if (ncp > 0) {
+            k_z_forward<<<pad * ncp, kT2, 0, st>>>(a, c0, pad, scratch, meta, Z);
+            for (int I = a.np_max / kNB - 1; I >= 0; --I)
+                k_z_back<<<pad * ncp, kT2, 0, st>>>(a, c0, I, pad, scratch, meta, Z);
+        }
     }
     return hipGetLastError();
 }
