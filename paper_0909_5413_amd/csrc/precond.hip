@@ -1001,13 +1001,26 @@ __global__ __launch_bounds__(kT2, 2) void k_z_forward(PrecondArgs a, long long c
 }
 
 // Centre rows, back solve of block row I: L_II^T X_I = W_I - L[below, I]^T
-// X[below]; the slot's block rows are visited from its last one up.
-__global__ __launch_bounds__(kT2, 2) void k_z_back(PrecondArgs a, long long c0, int I,
-                                                   int nslots_pad,
-                                                   const double* __restrict__ scratch,
-                                                   const int4* __restrict__ meta,
-                                                   double* __restrict__ Z) {
-    __shared__ ZLds s;
+// X[below]; the slot's block rows are visited from its last one up.  One wave
+// per (slot, 64 right-hand sides): the product (32 rows x 64 columns, eight
+// 16x16 MFMA tiles) takes its operands straight from memory into registers,
+// each loaded once, the next chunk of 16 k in flight; W_I and the result move
+// through LDS with coalesced accesses, and the 32x32 triangular solve runs one
+// right-hand side per lane, unrolled in registers.
+constexpr int kZT = 64;   // threads of the back-solve kernel (one wave)
+
+struct ZBackLds {
+    double T[kNB][kZCols + 1];   // W_I - product, then X_I
+    double L[kNB][kNB + 1];      // L_II
+    double invd[kNB];
+};
+
+__global__ __launch_bounds__(kZT) void k_z_back(PrecondArgs a, long long c0, int I,
+                                                int nslots_pad,
+                                                const double* __restrict__ scratch,
+                                                const int4* __restrict__ meta,
+                                                double* __restrict__ Z) {
+    __shared__ ZBackLds s;
     const int slot = blockIdx.x % nslots_pad, cp = blockIdx.x / nslots_pad;
     const int4 m = meta[slot];
     const int np = m.x, n_omega = m.y, n_c = m.z;
@@ -1015,20 +1028,133 @@ __global__ __launch_bounds__(kT2, 2) void k_z_back(PrecondArgs a, long long c0, 
     const int I0 = I * kNB;
     const int p = np - n_omega;
     if (!m.w || col0 >= n_c || I0 >= np || I0 + kNB <= p) return;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     const int ncol = n_c - col0 < kZCols ? n_c - col0 : kZCols;
-    const int q0 = np - n_c, ib = q0 / kNB;
+    const int w_lo = (np - n_c) / kNB * kNB;   // W is zero above this row
     const double* A = scratch + (size_t)slot * slot_elems64(a.np_max);
-    double* Zc = Z + a.zoff[c0 + slot];
-    zsolve_block<true>(A, I0, I0 + kNB, np, Zc, n_omega, p, col0, ncol, q0, ib * kNB, s);
-    if (tid < ncol) {
-        for (int r = kNB - 1; r >= 0; --r) {
-            double v = s.acc[r][tid];
-            for (int r2 = r + 1; r2 < kNB; ++r2) v = __builtin_fma(-s.D[r2][r], s.acc[r2][tid], v);
-            s.acc[r][tid] = v * s.invd[r];
+    double* Zc = Z + a.zoff[c0 + slot] + (size_t)col0 * n_omega - p;   // Zc[c * n_omega + k]
+    // W_I (zero above w_lo and in the padding rows), coalesced along each Z row
+    for (int idx = lane; idx < kNB * kZCols; idx += kZT) {
+        const int c = idx / kNB, r = idx % kNB;
+        const int row = I0 + r;
+        s.T[r][c] = (c < ncol && row >= w_lo && row >= p) ? Zc[(size_t)c * n_omega + row] : 0.0;
+    }
+    for (int idx = lane; idx < kNB * kNB; idx += kZT) {
+        const int i = idx / kNB, j = idx % kNB;
+        s.L[i][j] = (j <= i) ? A[roff(I0 + i) + I0 + j] : 0.0;
+    }
+    // product over k in [I0 + 32, np)
+    const int i16 = lane & 15, g = lane >> 4;
+    const int nchunk = (np - I0 - kNB) / 16;   // even
+    d4v acc[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = d4v{0.0, 0.0, 0.0, 0.0};
+    if (nchunk > 0) {
+        const double* zr[4];
+        bool zv[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            zv[ct] = 16 * ct + i16 < ncol;
+            zr[ct] = Zc + (size_t)(zv[ct] ? 16 * ct + i16 : 0) * n_omega;
         }
-        for (int r = 0; r < kNB; ++r)
-            if (I0 + r >= p) Zc[(size_t)(col0 + tid) * n_omega + (I0 + r - p)] = s.acc[r][tid];
+        struct Buf {
+            double a[2][4], b[4][4];
+        } q0, q1;
+        auto load = [&](Buf& d, int ch) {
+            const int k = I0 + kNB + 16 * ch + 4 * g;
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const double* lr = A + roff(k + st) + I0 + i16;
+                d.a[0][st] = lr[0];
+                d.a[1][st] = lr[16];
+            }
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                for (int st = 0; st < 4; ++st) d.b[ct][st] = zv[ct] ? zr[ct][k + st] : 0.0;
+        };
+        auto mma = [&](const Buf& d) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < 4; ++ct)
+                        acc[rt][ct] = mfma_f64(d.a[rt][st], d.b[ct][st], acc[rt][ct]);
+        };
+        // two register buffers in turn (nchunk is even)
+        load(q0, 0);
+        for (int ch = 0; ch < nchunk; ch += 2) {
+            load(q1, ch + 1);
+            mma(q0);
+            if (ch + 2 < nchunk) load(q0, ch + 2);
+            mma(q1);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s.T[16 * rt + g + 4 * v][16 * ct + i16] -= acc[rt][ct][v];
+    if (lane < kNB) s.invd[lane] = 1.0 / s.L[lane][lane];
+    __syncthreads();
+    // L_II^T x = t for right-hand side `lane`, from the last row up
+    {
+        double x[kNB];
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) x[r] = s.T[r][lane];
+#pragma unroll
+        for (int r = kNB - 1; r >= 0; --r) {
+            x[r] *= s.invd[r];
+#pragma unroll
+            for (int r2 = 0; r2 < r; ++r2) x[r2] = __builtin_fma(-s.L[r][r2], x[r], x[r2]);
+        }
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) s.T[r][lane] = x[r];
+    }
+    __syncthreads();
+    for (int idx = lane; idx < kNB * kZCols; idx += kZT) {
+        const int c = idx / kNB, r = idx % kNB;
+        const int row = I0 + r;
+        if (c < ncol && row >= p) Zc[(size_t)c * n_omega + row] = s.T[r][c];
+    }
+}
+
+// z[c's points] = Z_c v[members of c], one workgroup per cell: the member
+// values of v gathered into LDS, then Z_c streamed once from HBM.  Each wave
+// takes four rows at a time, a 16-lane group per row (so one load instruction
+// reads four 128-byte row segments), four independent loads per lane in
+// flight, and one 16-lane reduction per row.  FP32 rows accumulate with Kahan
+// compensation.
+template <typename T>
+__device__ __forceinline__ double row_dot(const T* __restrict__ zr, const T* vs, int n_omega,
+                                          int ph) {
+    if (sizeof(T) == 8) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int q = ph;
+        for (; q + 48 < n_omega; q += 64) {
+            const double z0 = zr[q], z1 = zr[q + 16], z2 = zr[q + 32], z3 = zr[q + 48];
+            a0 = __builtin_fma(z0, (double)vs[q], a0);
+            a1 = __builtin_fma(z1, (double)vs[q + 16], a1);
+            a2 = __builtin_fma(z2, (double)vs[q + 32], a2);
+            a3 = __builtin_fma(z3, (double)vs[q + 48], a3);
+        }
+        for (; q < n_omega; q += 16) a0 = __builtin_fma((double)zr[q], (double)vs[q], a0);
+        return (a0 + a1) + (a2 + a3);
+    } else {
+        Kahan32 a0, a1;
+        int q = ph;
+        for (; q + 16 < n_omega; q += 32) {
+            const float z0 = (float)zr[q], z1 = (float)zr[q + 16];
+            a0.add(z0 * (float)vs[q]);
+            a1.add(z1 * (float)vs[q + 16]);
+        }
+        for (; q < n_omega; q += 16) a0.add((float)zr[q] * (float)vs[q]);
+        return a0.value() + a1.value();
     }
 }
 
@@ -1048,22 +1174,16 @@ __global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T*
     for (int k = tid; k < n_omega; k += kThreads) vs[k] = (T)v[member_index(rb, re, nr, k)];
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
+    const int grp = lane >> 4, ph = lane & 15;
     const T* Zc = Z + a.zoff[c];
     const int own = a.cell_start[c];
-    for (int r = wave; r < n_c; r += kThreads / 64) {
-        const T* zr = Zc + (size_t)r * n_omega;
-        double sum;
-        if (sizeof(T) == 8) {
-            double acc = 0.0;
-            for (int q = lane; q < n_omega; q += 64)
-                acc = __builtin_fma((double)zr[q], (double)vs[q], acc);
-            sum = wave_sum(acc);
-        } else {
-            Kahan32 acc;
-            for (int q = lane; q < n_omega; q += 64) acc.add((float)zr[q] * (float)vs[q]);
-            sum = wave_sum(acc.value());
-        }
-        if (lane == 0) z[own + r] = sum;
+    for (int r0 = 4 * wave; r0 < n_c; r0 += 4 * (kThreads / 64)) {
+        const int r = r0 + grp;
+        double sum = 0.0;
+        if (r < n_c) sum = row_dot<T>(Zc + (size_t)r * n_omega, vs, n_omega, ph);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, RBF_WAVE);
+        if (ph == 0 && r < n_c) z[own + r] = sum;
     }
 }
 
@@ -1085,7 +1205,7 @@ hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scrat
         if (ncp > 0) {
             k_z_forward<<<pad * ncp, kT2, 0, st>>>(a, c0, pad, scratch, meta, Z);
             for (int I = a.np_max / kNB - 1; I >= 0; --I)
-                k_z_back<<<pad * ncp, kT2, 0, st>>>(a, c0, I, pad, scratch, meta, Z);
+                k_z_back<<<pad * ncp, kZT, 0, st>>>(a, c0, I, pad, scratch, meta, Z);
         }
     }
     return hipGetLastError();
