@@ -379,34 +379,35 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     RBF_TRY(p->alloc_n(&Z, ztot));
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
-    const long long slot_elems =
-        is64 ? rbf::slot_elems64(p->np_max) : (long long)p->np_max * p->np_max;
-    // cells per batch (FP64: one scratch matrix per cell of a batch that the
-    // lockstep launches advance together; FP32: resident workgroups of the
-    // persistent kernel)
-    long long nslots = is64 ? std::min<long long>(nc, 8192) : std::min<long long>(nc, 2LL * cus);
+    const long long slot_elems = rbf::slot_elems64(p->np_max);
+    // cells per batch: one scratch matrix per cell of a batch that the
+    // lockstep launches advance together
+    long long nslots = std::min<long long>(nc, 8192);
     const long long max_scratch = 12LL << 30;
     while (nslots > cus && nslots * slot_elems * (long long)sizeof(T) > max_scratch) nslots /= 2;
     if (nslots > 8) nslots &= ~7LL;
     if (nslots < 1) nslots = 1;
     const long long pad = (nslots + 7) / 8 * 8;
-    T* scratch;
+    T* scratch = nullptr;
+    T* lt = nullptr;
     int* status = nullptr;
     int4* meta = nullptr;
-    double* lt = nullptr;
+    int* lvl = nullptr;
     rbf_status s = p->alloc_n(&scratch, nslots * slot_elems);
-    if (s != RBF_OK) {
-        p->release(Z);
-        return s;
-    }
-    s = p->alloc_n(&status, nc);
-    if (s == RBF_OK && is64) s = p->alloc_n(&meta, pad);
-    if (s == RBF_OK && is64) s = p->alloc_n(&lt, 2 * pad * 1024);
-    if (s != RBF_OK) {
-        p->release(Z);
-        p->release(scratch);
+    if (s == RBF_OK) s = p->alloc_n(&status, nc);
+    if (s == RBF_OK) s = p->alloc_n(&meta, pad);
+    if (s == RBF_OK) s = p->alloc_n(&lvl, pad);
+    if (s == RBF_OK) s = p->alloc_n(&lt, 2 * pad * 1024);
+    auto release_all = [&]() {
+        if (scratch) p->release(scratch);
         if (status) p->release(status);
         if (meta) p->release(meta);
+        if (lvl) p->release(lvl);
+        if (lt) p->release(lt);
+    };
+    if (s != RBF_OK) {
+        p->release(Z);
+        release_all();
         return s;
     }
     rbf::PrecondArgs a = p->pc_args();
@@ -414,18 +415,16 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     if (is64)
         e = rbf::launch_precond_setup64(a, reinterpret_cast<double*>(Z),
                                         reinterpret_cast<double*>(scratch), (int)nslots, meta,
-                                        lt, status, st);
+                                        reinterpret_cast<double*>(lt), lvl, status, st);
     else
         e = rbf::launch_precond_setup32(a, reinterpret_cast<float*>(Z),
-                                        reinterpret_cast<float*>(scratch), (int)nslots, status, st);
+                                        reinterpret_cast<float*>(scratch), (int)nslots, meta,
+                                        reinterpret_cast<float*>(lt), lvl, status, st);
     std::vector<int> hs(nc);
     if (e == hipSuccess)
         e = hipMemcpyAsync(hs.data(), status, sizeof(int) * nc, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    p->release(scratch);
-    p->release(status);
-    if (meta) p->release(meta);
-    if (lt) p->release(lt);
+    release_all();
     if (e != hipSuccess) {
         p->release(Z);
         return fail(RBF_EDEVICE, "preconditioner setup: %s", hipGetErrorString(e));

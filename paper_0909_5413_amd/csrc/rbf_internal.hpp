@@ -100,20 +100,21 @@ struct PrecondArgs {
     int nc_max;             // largest number of points in one cell
     long long ncells;
 };
-// Build Z_c (centre rows of the inverse of the local matrix) for all cells.
-// FP64: batches of nslots cells; scratch holds nslots * slot_elems64(np_max)
-// doubles, meta 8 * ceil(nslots / 8) records, lt 2 * 1024 * 8 * ceil(nslots / 8)
-// doubles.  status[c]: 0 ok, else the failing pivot (1-based).
+// Build Z_c (centre rows of the inverse of the local matrix) for all cells, in
+// batches of nslots cells.  scratch holds nslots * slot_elems64(np_max)
+// elements, meta and lvl 8 * ceil(nslots / 8) entries, lt 2 * 1024 * 8 *
+// ceil(nslots / 8) elements.  status[c]: 0 ok, -k after the k-th diagonal
+// shift level (FP32 only), > 0 the failing pivot (1-based).
 __host__ __device__ inline long long slot_elems64(int np_max) {
     const long long b = np_max / 32;
     return 512LL * b * (b + 1);
 }
 hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scratch,
-                                  int nslots, int4* meta, double* lt, int* status, hipStream_t st);
-// FP32: persistent grid of nslots workgroups, scratch nslots * np_max * np_max
-// floats; status[c]: 0 ok, -k after k-th shift level, > 0 failing pivot.
+                                  int nslots, int4* meta, double* lt, int* lvl, int* status,
+                                  hipStream_t st);
 hipError_t launch_precond_setup32(const PrecondArgs& a, float* Z, float* scratch,
-                                  int nslots, int* status, hipStream_t st);
+                                  int nslots, int4* meta, float* lt, int* lvl, int* status,
+                                  hipStream_t st);
 // z[own points of c] = Z_c v[members of c], every cell.
 hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const double* v,
                                double* z, hipStream_t st);
