@@ -88,6 +88,7 @@ struct rbf_problem {
     double sc32 = 0;                   // FP32 coordinate scale
     long long interactions = -1;
     double* etab = nullptr;            // e^{-n/128}, n < ntab (device), or NULL
+    double* t32 = nullptr;             // 2^(j/32), j < 32 (device)
     int ntab = 0;
     float* w32 = nullptr;              // FP32 weights workspace of the FP32 matvec
 
@@ -110,6 +111,7 @@ struct rbf_problem {
     int* flag = nullptr;
     double* lam = nullptr;             // last solution, sorted order
     bool solved = false;
+    rbf::NeighborLists nl{};           // matvec neighbour lists (nunits == 0: none)
     std::vector<double> history;
 
     rbf_status alloc(void** out, size_t bytes_) {
@@ -156,6 +158,7 @@ struct rbf_problem {
         a.norm = 1.0 / (2.0 * kPi * sigma * sigma);
         a.etab = etab;
         a.ntab = ntab;
+        a.t32 = t32;
         return a;
     }
     rbf::Matvec32Args mv32_args() const {
@@ -203,6 +206,59 @@ rbf_status check_args(long long n, double sigma, double cutoff, int overlap) {
 }
 
 // The setup pipeline on device arrays d_pts (n x 2) and d_vals (n or NULL).
+// Neighbour lists of the matvec (skipped when some 3x3 block of cells holds
+// more sources than a list-driven launch can stage; the candidate kernels then
+// serve every matvec).
+rbf_status build_lists(rbf_problem* p, hipStream_t st) {
+    const rbf::Grid& g = p->g;
+    const long long nc = p->ncells;
+    std::vector<int2> units;
+    int max_nb = 0;
+    for (long long c = 0; c < nc; ++c) {
+        const int own = p->cs_host[c + 1] - p->cs_host[c];
+        if (own == 0) continue;
+        const int cx = (int)(c % g.ncx), cy = (int)(c / g.ncx);
+        const int xlo = std::max(cx - 1, 0), xhi = std::min(cx + 1, g.ncx - 1);
+        long long nb = 0;
+        for (int ny = std::max(cy - 1, 0); ny <= std::min(cy + 1, g.ncy - 1); ++ny)
+            nb += p->cs_host[(long long)ny * g.ncx + xhi + 1] - p->cs_host[(long long)ny * g.ncx + xlo];
+        if (nb > rbf::kListMaxNb) return RBF_OK;
+        max_nb = std::max(max_nb, (int)nb);
+        for (int t = 0; t < own; t += 64) units.push_back(int2{(int)c, p->cs_host[c] + t});
+    }
+    const int nu = (int)units.size();
+    if (nu == 0) return RBF_OK;
+    int2* unit = nullptr;
+    int *len = nullptr, *nbv = nullptr;
+    long long* off = nullptr;
+    unsigned short* idx = nullptr;
+    RBF_TRY(p->alloc_n(&unit, nu));
+    RBF_TRY(p->alloc_n(&len, nu));
+    RBF_TRY(p->alloc_n(&nbv, nu));
+    RBF_TRY(p->alloc_n(&off, nu + 1));
+    HIP_TRY(hipMemcpyAsync(unit, units.data(), sizeof(int2) * nu, hipMemcpyHostToDevice, st));
+    const rbf::MatvecArgs a = p->mv_args();
+    HIP_TRY(rbf::launch_list_count(a, unit, nu, len, nbv, st));
+    std::vector<int> hl(nu);
+    HIP_TRY(hipMemcpyAsync(hl.data(), len, sizeof(int) * nu, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<long long> ho(nu + 1);
+    ho[0] = 0;
+    for (int u = 0; u < nu; ++u) ho[u + 1] = ho[u] + 64LL * hl[u];
+    RBF_TRY(p->alloc_n(&idx, ho[nu]));
+    HIP_TRY(hipMemcpyAsync(off, ho.data(), sizeof(long long) * (nu + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(rbf::launch_list_fill(a, unit, nu, off, len, idx, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    p->release(nbv);
+    p->nl.unit = unit;
+    p->nl.off = off;
+    p->nl.len = len;
+    p->nl.idx = idx;
+    p->nl.nunits = nu;
+    p->nl.max_nb = max_nb;
+    return RBF_OK;
+}
+
 rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals, hipStream_t st) {
     const long long n = p->n;
     double* work;
@@ -311,8 +367,15 @@ rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals,
                                st));
         HIP_TRY(hipStreamSynchronize(st));
     }
+    {
+        double tab[32];
+        for (int j = 0; j < 32; ++j) tab[j] = (double)std::exp2((long double)j / 32.0L);
+        RBF_TRY(p->alloc_n(&p->t32, 32));
+        HIP_TRY(hipMemcpyAsync(p->t32, tab, sizeof tab, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
     RBF_TRY(p->alloc_n(&p->w32, n));
-    return RBF_OK;
+    return build_lists(p, st);
 }
 
 rbf_status create(const double* pts, const double* vals, bool on_device, long long n,
@@ -462,10 +525,17 @@ rbf_status precond_setup(rbf_problem* p, rbf_precision prec, hipStream_t st) {
 }
 
 rbf_status matvec(rbf_problem* p, rbf_precision prec, const double* w, double* y, hipStream_t st) {
+    const bool lists = p->nl.nunits > 0;
     if (prec == RBF_FP64) {
-        HIP_TRY(rbf::launch_matvec64(p->mv_args(), w, y, nullptr, st));
+        if (lists)
+            HIP_TRY(rbf::launch_matvec64_lists(p->mv_args(), p->nl, w, y, st));
+        else
+            HIP_TRY(rbf::launch_matvec64(p->mv_args(), w, y, nullptr, st));
     } else {
-        HIP_TRY(rbf::launch_matvec32(p->mv32_args(), w, p->w32, y, p->n, st));
+        if (lists)
+            HIP_TRY(rbf::launch_matvec32_lists(p->mv32_args(), p->nl, w, y, st));
+        else
+            HIP_TRY(rbf::launch_matvec32(p->mv32_args(), w, p->w32, y, p->n, st));
     }
     return RBF_OK;
 }

@@ -178,6 +178,214 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec32(Matvec32Args a, const f
     }
 }
 
+// ---- neighbour lists ---------------------------------------------------------
+
+// The three row ranges of cell c's 3x3 block (sorted-order [b, e) per row,
+// empty rows outside the grid) and the first cell column of each range.
+struct Rows {
+    int b[3], e[3], base[3];   // base: local index of the range's first source
+    int n;                     // n_nb
+    int xlo, cx, cy;
+};
+
+__device__ __forceinline__ Rows block_rows(const int* __restrict__ scell, const Grid& g, int c) {
+    Rows r;
+    const int ncx = g.ncx, ncy = g.ncy;
+    r.cx = c % ncx;
+    r.cy = c / ncx;
+    r.xlo = r.cx > 0 ? r.cx - 1 : 0;
+    const int xhi = r.cx + 1 < ncx ? r.cx + 1 : ncx - 1;
+    int tot = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int ny = r.cy + d - 1;
+        int b = 0, e = 0;
+        if (ny >= 0 && ny < ncy) {
+            b = scell[ny * ncx + r.xlo];
+            e = scell[ny * ncx + xhi + 1];
+        }
+        r.b[d] = b;
+        r.e[d] = e;
+        r.base[d] = tot;
+        tot += e - b;
+    }
+    r.n = tot;
+    return r;
+}
+
+// Count (kFill = false) or write (kFill = true) each lane's in-cutoff sources;
+// the decision d2 <= rc2 is the one the candidate kernel takes, bit for bit.
+template <bool kFill>
+__global__ __launch_bounds__(64) void k_list_build(MatvecArgs a, const int2* __restrict__ unit,
+                                                   int* __restrict__ len, int* __restrict__ nb,
+                                                   const long long* __restrict__ off,
+                                                   unsigned short* __restrict__ idx) {
+    const int u = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int2 uc = unit[u];
+    const int c = uniform(uc.x), t0 = uniform(uc.y);
+    const int t1 = uniform(a.scell[c + 1]);
+    const Rows r = block_rows(a.scell, a.g, c);
+    const int t = t0 + lane;
+    const bool act = t < t1;
+    const double xi = act ? a.sx[t] : 0.0, yi = act ? a.sy[t] : 0.0;
+    int cnt = 0;
+    unsigned short* mine = kFill ? idx + off[u] + 4 * lane : nullptr;
+    for (int d = 0; d < 3; ++d) {
+        const int b = uniform(r.b[d]), e = uniform(r.e[d]), base = uniform(r.base[d]);
+        for (int s = b; s < e; ++s) {
+            const double dx = xi - a.sx[s], dy = yi - a.sy[s];
+            const bool in = act && __builtin_fma(dx, dx, dy * dy) <= a.rc2;
+            if (in) {
+                if (kFill) mine[256 * (cnt >> 2) + (cnt & 3)] = (unsigned short)(base + s - b);
+                ++cnt;
+            }
+        }
+    }
+    if (kFill) {
+        const int L = len[u];
+        for (int k = cnt; k < L; ++k) mine[256 * (k >> 2) + (k & 3)] = (unsigned short)r.n;
+    } else {
+        int m = cnt;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int v = __shfl_xor(m, o, 64);
+            m = v > m ? v : m;
+        }
+        if (lane == 0) {
+            len[u] = (m + 3) & ~3;
+            nb[u] = r.n;
+        }
+    }
+}
+
+// y[t] = norm * sum over the target's list of w[s] exp(mk d2): the unit's
+// sources staged in LDS as 32-byte records (x, y, w), the null source at the
+// cell centre with weight 0, the exponential from a 32-entry table (also in
+// LDS); four list entries per 8-byte load, loaded two loop passes ahead.
+__global__ __launch_bounds__(64) void k_matvec64_lists(MatvecArgs a, NeighborLists nl,
+                                                       const double* __restrict__ w,
+                                                       double* __restrict__ y) {
+    extern __shared__ double smem[];
+    const int u = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int2 uc = nl.unit[u];
+    const int c = uniform(uc.x), t0 = uniform(uc.y);
+    const int t1 = uniform(a.scell[c + 1]);
+    const Rows r = block_rows(a.scell, a.g, c);
+    const int n = r.n;
+    double* T32 = smem;                 // 32 entries
+    double4* S = reinterpret_cast<double4*>(smem + 32);
+    if (lane < 32) T32[lane] = a.t32[lane];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int b = r.b[d], cnt = r.e[d] - r.b[d], base = r.base[d];
+        for (int q = lane; q < cnt; q += 64)
+            S[base + q] = double4{a.sx[b + q], a.sy[b + q], w[b + q], 0.0};
+    }
+    const double xc = a.g.x0 + (r.cx + 0.5) * a.g.L, yc = a.g.y0 + (r.cy + 0.5) * a.g.L;
+    if (lane == 0) S[n] = double4{xc, yc, 0.0, 0.0};
+    const int t = t0 + lane;
+    const bool act = t < t1;
+    const double xi = act ? a.sx[t] : xc;
+    const double yi = act ? a.sy[t] : yc;
+    const int L = uniform(nl.len[u]);   // multiple of 4, >= 4
+    const uint2* lp = reinterpret_cast<const uint2*>(nl.idx + nl.off[u]) + lane;
+    // two list registers in turn, each reloaded two passes ahead (no copies)
+    uint2 qa = lp[0];
+    uint2 qb = L > 4 ? lp[64] : uint2{0u, 0u};
+    __syncthreads();
+    double acc0 = 0.0, acc1 = 0.0;
+    auto four = [&](const uint2 q4) {
+        const int q[4] = {(int)(q4.x & 0xffff), (int)(q4.x >> 16), (int)(q4.y & 0xffff),
+                          (int)(q4.y >> 16)};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double4 s = S[q[j]];
+            const double dx = xi - s.x, dy = yi - s.y;
+            const double e = exp_neg_t32(__builtin_fma(dx, dx, dy * dy) * a.mk, T32);
+            if (j & 1)
+                acc1 = __builtin_fma(s.z, e, acc1);
+            else
+                acc0 = __builtin_fma(s.z, e, acc0);
+        }
+    };
+    for (int k = 0; k < L; k += 8) {
+        four(qa);
+        if (k + 8 < L) qa = lp[64 * (k / 4 + 2)];
+        if (k + 4 < L) {
+            four(qb);
+            if (k + 12 < L) qb = lp[64 * (k / 4 + 3)];
+        }
+    }
+    if (act) y[t] = (acc0 + acc1) * a.norm;
+}
+
+// FP32 form: the staged sources are moved into the target cell's frame (the
+// scaled cell-relative coordinates plus the cell offset), so d2 is the negated
+// base-2 exponent; Kahan-compensated FP32 accumulation, FP64 output.
+__global__ __launch_bounds__(64) void k_matvec32_lists(Matvec32Args a, NeighborLists nl,
+                                                       const double* __restrict__ w,
+                                                       double* __restrict__ y) {
+    extern __shared__ double smem[];
+    const int u = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int2 uc = nl.unit[u];
+    const int c = uniform(uc.x), t0 = uniform(uc.y);
+    const int t1 = uniform(a.scell[c + 1]);
+    const Rows r = block_rows(a.scell, a.g, c);
+    const int n = r.n;
+    float2* XY = reinterpret_cast<float2*>(smem);
+    float* W = reinterpret_cast<float*>(smem) + 2 * (nl.max_nb + 1);
+    const int ncx = a.g.ncx;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int ny = r.cy + d - 1;
+        const int b = r.b[d], cnt = r.e[d] - r.b[d], base = r.base[d];
+        for (int q = lane; q < cnt; q += 64) {
+            const int s = b + q;
+            // cell column of s within the row range
+            int nx = r.xlo;
+            while (nx + 1 < ncx && a.scell[ny * ncx + nx + 1] <= s) ++nx;
+            XY[base + q] = float2{a.sx[s] + (float)(nx - r.cx) * a.Ls,
+                                  a.sy[s] + (float)(d - 1) * a.Ls};
+            W[base + q] = (float)w[s];
+        }
+    }
+    if (lane == 0) {
+        XY[n] = float2{0.f, 0.f};
+        W[n] = 0.f;
+    }
+    const int t = t0 + lane;
+    const bool act = t < t1;
+    const float xi = act ? a.sx[t] : 0.f, yi = act ? a.sy[t] : 0.f;
+    __syncthreads();
+    const int L = uniform(nl.len[u]);   // multiple of 4, >= 4
+    const uint2* lp = reinterpret_cast<const uint2*>(nl.idx + nl.off[u]) + lane;
+    uint2 qa = lp[0];
+    uint2 qb = L > 4 ? lp[64] : uint2{0u, 0u};
+    Kahan32 acc;
+    auto four = [&](const uint2 q4) {
+        const int q[4] = {(int)(q4.x & 0xffff), (int)(q4.x >> 16), (int)(q4.y & 0xffff),
+                          (int)(q4.y >> 16)};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float2 s = XY[q[j]];
+            const float dx = xi - s.x, dy = yi - s.y;
+            acc.add(W[q[j]] * exp2_f32(-__builtin_fmaf(dx, dx, dy * dy)));
+        }
+    };
+    for (int k = 0; k < L; k += 8) {
+        four(qa);
+        if (k + 8 < L) qa = lp[64 * (k / 4 + 2)];
+        if (k + 4 < L) {
+            four(qb);
+            if (k + 12 < L) qb = lp[64 * (k / 4 + 3)];
+        }
+    }
+    if (act) y[t] = acc.value() * a.norm;
+}
+
 inline unsigned mv_grid(long long ncells) {
     long long b = (ncells + kMvWaves - 1) / kMvWaves;
     return (unsigned)(b < 2048 ? (b > 0 ? b : 1) : 2048);
@@ -214,6 +422,36 @@ hipError_t launch_matvec32(const Matvec32Args& a, const double* w, float* w32, d
     long long nb = (n + kMvThreads - 1) / kMvThreads;
     k_to_f32<<<(unsigned)(nb < 4096 ? (nb > 0 ? nb : 1) : 4096), kMvThreads, 0, st>>>(w, n, w32);
     k_matvec32<<<mv_grid(a.g.ncells()), kMvThreads, 0, st>>>(a, a.sx, a.sy, w32, a.scell, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_count(const MatvecArgs& a, const int2* unit, int nunits, int* len, int* nb,
+                             hipStream_t st) {
+    if (nunits > 0)
+        k_list_build<false><<<nunits, 64, 0, st>>>(a, unit, len, nb, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_fill(const MatvecArgs& a, const int2* unit, int nunits,
+                            const long long* off, const int* len, unsigned short* idx,
+                            hipStream_t st) {
+    if (nunits > 0)
+        k_list_build<true><<<nunits, 64, 0, st>>>(a, unit, const_cast<int*>(len), nullptr, off,
+                                                  idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec64_lists(const MatvecArgs& a, const NeighborLists& nl, const double* w,
+                                 double* y, hipStream_t st) {
+    const size_t lds = sizeof(double) * (32 + 4 * (size_t)(nl.max_nb + 1));
+    if (nl.nunits > 0) k_matvec64_lists<<<nl.nunits, 64, lds, st>>>(a, nl, w, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec32_lists(const Matvec32Args& a, const NeighborLists& nl, const double* w,
+                                 double* y, hipStream_t st) {
+    const size_t lds = sizeof(float) * 3 * (size_t)(nl.max_nb + 1);
+    if (nl.nunits > 0) k_matvec32_lists<<<nl.nunits, 64, lds, st>>>(a, nl, w, y);
     return hipGetLastError();
 }
 

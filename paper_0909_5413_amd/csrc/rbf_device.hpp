@@ -67,6 +67,34 @@ __device__ __forceinline__ double exp_neg_tab(double x, const double* __restrict
     return T[n] * p;
 }
 
+// ---------------------------------------------------------------------------
+// exp(x) for -700 < x <= 0 from a 32-entry table T[j] = 2^(j/32) (correctly
+// rounded, held in LDS by the caller; 256 bytes, so lanes never conflict on
+// a bank): with k = rint(32 x / ln2) = 32 n + j (0 <= j < 32) and
+// r = x - k ln2 / 32 (|r| <= ln2/64, ln2/32 split exactly as above),
+// exp(x) = 2^n T[j] exp(r), exp(r) by its degree-6 Taylor polynomial
+// (truncation below r^7/7! < 3.5e-18).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_neg_t32(double x, const double* T) {
+    const double kLog2e32 = 0x1.71547652b82fep+5;     // 32/ln2 rounded
+    const double kShift = 0x1.8p52;
+    const double kLn2Hi32 = 0x1.62e42ff000000p-6;     // ln2 head / 32 (exact)
+    const double kLn2Lo32 = -0x1.718432a1b0e26p-40;   // ln2 tail / 32 (exact)
+    const double t = __builtin_fma(x, kLog2e32, kShift);
+    const double kf = t - kShift;
+    const int k = (int)__double2loint(t);
+    double r = __builtin_fma(kf, -kLn2Hi32, x);
+    r = __builtin_fma(kf, -kLn2Lo32, r);
+    double p = 0x1.6c16c16c16c17p-10;                 // 1/6!
+    p = __builtin_fma(p, r, 0x1.1111111111111p-7);    // 1/5!
+    p = __builtin_fma(p, r, 0x1.5555555555555p-5);    // 1/4!
+    p = __builtin_fma(p, r, 0x1.5555555555555p-3);    // 1/3!
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(T[k & 31] * p, k >> 5);
+}
+
 // 2^x in FP32 on the hardware transcendental unit (v_exp_f32).
 __device__ __forceinline__ float exp2_f32(float x) { return __builtin_amdgcn_exp2f(x); }
 

@@ -65,6 +65,7 @@ struct MatvecArgs {
     double norm;            // 1 / (2 pi sigma^2)
     const double* etab;     // e^{-n/128}, n < ntab, or NULL (no table)
     int ntab;
+    const double* t32;      // 2^(j/32), j < 32
 };
 // entries of the exponential table held in LDS (covers cutoffs up to ~6.3 sigma)
 constexpr int kExpTableMax = 2560;
@@ -86,6 +87,40 @@ struct Matvec32Args {
 // w32: n floats of workspace (the weights rounded to FP32)
 hipError_t launch_matvec32(const Matvec32Args& a, const double* w, float* w32, double* y,
                            long long n, hipStream_t st);
+
+// ---- neighbour lists (matvec.hip) --------------------------------------------
+// A unit is up to 64 targets of one cell (one per lane) together with the
+// sources of the 3x3 block of cells around it, indexed locally: the row ranges
+// dy = -1, 0, 1 in that order, each the contiguous sorted range of up to three
+// cells, concatenated (n_nb sources).  A unit's list holds, per lane, the local
+// indices of the target's in-cutoff sources in local order, padded to the
+// unit's longest list (a multiple of 4) with the index n_nb of a null source;
+// entry k of lane l sits at off[u] + 256 (k / 4) + 4 l + k % 4, so one 8-byte
+// load fetches four indices.
+struct NeighborLists {
+    const int2* unit;          // (cell, first target) per unit
+    const long long* off;      // per unit, entries
+    const int* len;            // per unit, padded list length
+    const unsigned short* idx;
+    int nunits;
+    int max_nb;                // largest n_nb over the units
+};
+// Sources per neighbourhood that a list-driven launch can stage in LDS
+// (32-byte records).
+constexpr int kListMaxNb = 2047;
+// len[u] = the unit's padded list length (max in-cutoff count over its lanes,
+// rounded up to 4); nb[u] = its n_nb.
+hipError_t launch_list_count(const MatvecArgs& a, const int2* unit, int nunits, int* len,
+                             int* nb, hipStream_t st);
+hipError_t launch_list_fill(const MatvecArgs& a, const int2* unit, int nunits,
+                            const long long* off, const int* len, unsigned short* idx,
+                            hipStream_t st);
+// The same products as launch_matvec64 / launch_matvec32 (targets = sources),
+// driven by the lists: every evaluated pair is an interaction.
+hipError_t launch_matvec64_lists(const MatvecArgs& a, const NeighborLists& nl, const double* w,
+                                 double* y, hipStream_t st);
+hipError_t launch_matvec32_lists(const Matvec32Args& a, const NeighborLists& nl, const double* w,
+                                 double* y, hipStream_t st);
 
 // ---- preconditioner (precond.hip) --------------------------------------------
 struct PrecondArgs {

@@ -88,3 +88,51 @@ def test_device_exp_constants_accurate():
         ref = math.exp(float(x))
         worst = max(worst, abs(got - ref) / ref)
     assert worst < 4e-16, worst
+
+
+def _device_exp_t32(x):
+    """exp_neg_t32 step by step (fused multiply-adds rounded once, the table
+    entries 2^(j/32) correctly rounded as the host builds them)."""
+    src = open(os.path.join(ROOT, "paper_0909_5413_amd", "csrc", "rbf_device.hpp")).read()
+    body = src[src.index("double exp_neg_t32"):]
+    body = body[:body.index("return __builtin_amdgcn_ldexp")]
+    consts = dict(re.findall(r"const double (k\w+) = ([0-9a-fA-Fx.p+-]+);", body))
+    log2e32 = float.fromhex(consts["kLog2e32"])
+    shift = float.fromhex(consts["kShift"])
+    hi = float.fromhex(consts["kLn2Hi32"])
+    lo = float.fromhex(consts["kLn2Lo32"])
+    coefs = [float.fromhex(h) for h in re.findall(r"(0x[0-9a-f.]+p[+-]?\d+)\);?\s*// 1/", body)]
+    first = float.fromhex(re.search(r"double p = ([0-9a-fx.p+-]+);", body).group(1))
+    t = _fma(x, log2e32, shift)
+    kf = t - shift
+    k = int(kf)
+    r = _fma(kf, -hi, x)
+    r = _fma(kf, -lo, r)
+    p = first
+    for c in coefs + [0.5, 1.0, 1.0]:
+        p = _fma(p, r, c)
+    j, n = k & 31, k >> 5
+    tj = _exp2_frac(j)
+    return math.ldexp(tj * p, n)
+
+
+def _exp2_frac(j):
+    # 2^(j/32) to 60 significant digits, then rounded to a double
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    return float(Decimal(2) ** (Decimal(j) / Decimal(32)))
+
+
+def test_device_exp_table_constants_accurate():
+    """The table-driven exponential of the list matvec (its constants are the
+    Cody-Waite split of ln2 scaled by 1/32, exact): within a few units of the
+    last place of exp on the matvec's range and beyond."""
+    rng = np.random.default_rng(4)
+    xs = np.concatenate([rng.uniform(-18.0, 0.0, 400), rng.uniform(-600.0, -18.0, 50),
+                         [-18.0, -1e-300, 0.0, -math.log(2) / 64, -math.log(2) * 5.5]])
+    worst = 0.0
+    for x in xs:
+        got = _device_exp_t32(float(x))
+        ref = math.exp(float(x))
+        worst = max(worst, abs(got - ref) / ref)
+    assert worst < 5e-16, worst

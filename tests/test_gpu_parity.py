@@ -183,6 +183,32 @@ def test_centre_rows_are_inverse_rows(problems, name):
         assert res <= bound, (cell, res, bound)
 
 
+@pytest.mark.parametrize("name", ["mini", "ragged"])
+def test_centre_rows_fp32_backward_error(problems, name):
+    """FP32 Z_c (mixed form): backward error at FP32 level.  A block may carry
+    a diagonal shift mu <= 1000 n u32 phi(0) (shifted Cholesky), so
+    ||Z_c A_c - E_C|| <= (10 n u32 ||A_c|| + mu_max) ||Z_c||."""
+    say("zrows32", name)
+    h, P, pts, f, sigma, cutoff = problems[name]
+    _, (ncx, ncy) = R.rbf_grid(h)
+    from tests import bruteforce as bf
+    u32 = 2.0 ** -24
+    phi0 = 1.0 / (2 * np.pi * sigma * sigma)
+    for cell in (0, ncx + 1, (ncx * ncy) // 2, ncx * ncy - 1):
+        mem, Z = R.rbf_precond_block(h, cell, R.RBF_MIXED)
+        o_mem, kc, _ = P.rasm_block(cell, with_factor=False)
+        assert np.array_equal(mem, o_mem)
+        if Z.shape[0] == 0:
+            continue
+        Z = Z.astype(np.float64)
+        A = bf.dense_matrix(pts[mem], sigma, None)
+        n = len(mem)
+        E = np.eye(n)[n - kc:]
+        res = np.linalg.norm(Z @ A - E, 2)
+        bound = (10 * n * u32 * np.linalg.norm(A, 2) + 1000 * n * u32 * phi0) * np.linalg.norm(Z, 2)
+        assert res <= bound, (cell, res, bound)
+
+
 @pytest.mark.parametrize("name,rtol", [("mini", 1e-12), ("c0", 1e-10), ("ragged", 1e-12)])
 def test_solve_fp64(problems, name, rtol):
     say("solve64", name)
