@@ -94,9 +94,9 @@ __device__ __forceinline__ int member_index(const int* rb, const int* re, int nr
 // workgroup takes a 256-row tile below the diagonal block, updates it with the
 // finished block columns as MFMA tiles (the result lands in LDS), solves
 // x L_JJ^T = a for its rows by substitution (one row per thread, L_JJ
-// broadcast from LDS), and writes the rows back.  The workgroup of the first
-// tile then also forms and factors the next diagonal block, which only needs
-// rows it has just finished.  The centre rows of the inverse follow: one
+// broadcast from LDS), and writes the rows back.  A second launch then forms
+// and factors the next diagonal block of every slot, one small single-wave
+// workgroup each.  The centre rows of the inverse follow: one
 // launch for the forward solve on the trailing rows, one launch per block row
 // of the back solve.  Every launch carries thousands of independent
 // workgroups, so one cell's serial steps overlap with other cells' work.
@@ -185,15 +185,8 @@ __device__ __forceinline__ size_t roff(int row) {
 
 template <typename T>
 struct StepLds {
-    union {
-        T X[kNB][kXS];                // the tile's rows, one column per thread
-        struct {
-            T D[kNB][kNB + 1];        // the next diagonal block
-            T part[kWS][3][16][17];   // per-wave partial products of its tiles
-        } d;
-    } u;
+    T X[kNB][kXS];                    // the tile's rows, one column per thread
     T Lt[kTri];                       // L_JJ transposed (packed), reciprocal pivots on the diagonal
-    int flag;
 };
 
 // X[c][r] = A[R + r][J + c] - sum_{k < J} L[R + r][k] L[J + c][k] for the
@@ -345,64 +338,6 @@ __device__ __forceinline__ void trsm_tile(const T* Lt, int nrow, T (*X)[kXS]) {
     }
 #pragma unroll
     for (int q = 0; q < kNB; ++q) X[q][tid] = x[q];
-}
-
-// D = A[J0.., J0..] - L[J0.., 0:J0] L[J0.., 0:J0]^T on the three lower 16x16
-// tiles of the 32x32 diagonal block, J0 > 0: wave w multiplies all three
-// tiles over its quarter of the chunks (three independent MFMA chains), and
-// the four partial products are summed through LDS.
-template <typename T>
-__device__ __forceinline__ void syrk_diag(const T* __restrict__ A, int J0, T (*D)[kNB + 1],
-                                          T (*part)[3][16][17]) {
-    static_assert(kWS == 4, "four partial products");
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int i16 = lane & 15, g = lane >> 4;
-    const T* r0 = A + roff(J0 + i16) + 4 * g;        // rows J0 .. J0+15
-    const T* r1 = A + roff(J0 + 16 + i16) + 4 * g;   // rows J0+16 .. J0+31
-    v4<T> t00 = {0, 0, 0, 0}, t10 = t00, t11 = t00;
-    auto mma3 = [&](const v4<T>& a0, const v4<T>& a1) {
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            t00 = mfma(a0[st], a0[st], t00);
-            t10 = mfma(a1[st], a0[st], t10);
-            t11 = mfma(a1[st], a1[st], t11);
-        }
-    };
-    // chunks wave, wave + 4, ...: two register buffers in turn
-    const int nchunk = J0 / 16;
-    v4<T> p0 = {0, 0, 0, 0}, p1 = p0, q0 = p0, q1 = p0;
-    if (wave < nchunk) {
-        p0 = load4(r0 + 16 * wave);
-        p1 = load4(r1 + 16 * wave);
-    }
-    for (int ch = wave; ch < nchunk; ch += 2 * kWS) {
-        const bool second = ch + kWS < nchunk;
-        if (second) {
-            q0 = load4(r0 + 16 * (ch + kWS));
-            q1 = load4(r1 + 16 * (ch + kWS));
-        }
-        mma3(p0, p1);
-        if (ch + 2 * kWS < nchunk) {
-            p0 = load4(r0 + 16 * (ch + 2 * kWS));
-            p1 = load4(r1 + 16 * (ch + 2 * kWS));
-        }
-        if (second) mma3(q0, q1);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = out_row<T>(g, v);
-        part[wave][0][r][i16] = t00[v];
-        part[wave][1][r][i16] = t10[v];
-        part[wave][2][r][i16] = t11[v];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < 3 * 256; idx += kTS) {
-        const int t = idx >> 8, r = (idx >> 4) & 15, c = idx & 15;
-        const T sum = (part[0][t][r][c] + part[1][t][r][c]) + (part[2][t][r][c] + part[3][t][r][c]);
-        const int row = 16 * (t == 0 ? 0 : 1) + r, col = 16 * (t == 2 ? 1 : 0) + c;
-        D[row][col] = A[roff(J0 + row) + J0 + col] - sum;
-    }
 }
 
 // Factor the 32x32 diagonal block J0 (lower part of D) in wave 0's registers
@@ -634,16 +569,13 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
 }
 
 // Block column J: workgroup b takes the 256-row tile b / nslots_pad below the
-// diagonal block of slot b % nslots_pad; the first tile's workgroup then
-// factors diagonal block J + 32.  lt_in / lt_out: per slot, L_JJ and L_{J+32}
-// transposed with reciprocal pivots (two buffers, alternating with J).
+// diagonal block of slot b % nslots_pad.  lt_in: per slot, L_JJ transposed
+// with reciprocal pivots.
 template <typename T>
-__global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, long long c0, int J,
-                                                      int nslots_pad, T* __restrict__ scratch,
-                                                      int4* __restrict__ meta,
-                                                      int* __restrict__ status,
-                                                      const T* __restrict__ lt_in,
-                                                      T* __restrict__ lt_out) {
+__global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int nslots_pad,
+                                                      T* __restrict__ scratch,
+                                                      const int4* __restrict__ meta,
+                                                      const T* __restrict__ lt_in) {
     __shared__ StepLds<T> s;
     const int slot = blockIdx.x % nslots_pad, tile = blockIdx.x / nslots_pad;
     const int4 m = meta[slot];
@@ -658,23 +590,83 @@ __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, long long c
         if (j >= k) s.Lt[tri(k, j)] = lt_in[(size_t)slot * kNB * kNB + e];
     }
     if (J > 0)
-        update_tile<T>(A, J, R, nrow, s.u.X);
+        update_tile<T>(A, J, R, nrow, s.X);
     else
-        load_tile<T>(A, J, R, nrow, s.u.X);
+        load_tile<T>(A, J, R, nrow, s.X);
     __syncthreads();
-    trsm_tile<T>(s.Lt, nrow, s.u.X);
+    trsm_tile<T>(s.Lt, nrow, s.X);
     __syncthreads();
-    store_tile<T>(A, J, R, nrow, s.u.X);
-    if (tile == 0) {
-        __syncthreads();
-        syrk_diag<T>(A, J + kNB, s.u.d.D, s.u.d.part);
-        __syncthreads();
-        const int f = factor_diag_block<T>(A, J + kNB, s.u.d.D, &s.flag,
-                                           lt_out + (size_t)slot * kNB * kNB);
-        if (f && tid == 0) {
-            status[c0 + slot] = f;
-            meta[slot].w = 0;
+    store_tile<T>(A, J, R, nrow, s.X);
+}
+
+// Diagonal block J0 > 0 of every slot, one wave per slot: D = A[J0.., J0..] -
+// L[J0.., 0:J0] L[J0.., 0:J0]^T on its three lower 16x16 tiles (three MFMA
+// chains in one wave, operands in two register buffers, the A entries loaded
+// up front), then its Cholesky (factor_diag_block) into A and lt_out.
+constexpr int kDT = 64;
+
+template <typename T>
+struct DiagLds {
+    T D[kNB][kNB + 1];
+    int flag;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, int J0,
+                                                   T* __restrict__ scratch,
+                                                   int4* __restrict__ meta,
+                                                   int* __restrict__ status,
+                                                   T* __restrict__ lt_out) {
+    __shared__ DiagLds<T> s;
+    const int slot = blockIdx.x;
+    const int4 m = meta[slot];
+    const int np = m.x;
+    if (!m.w || J0 >= np) return;
+    const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
+    T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
+    T d00[4], d10[4], d11[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = out_row<T>(g, v);
+        d00[v] = A[roff(J0 + r) + J0 + i16];
+        d10[v] = A[roff(J0 + 16 + r) + J0 + i16];
+        d11[v] = A[roff(J0 + 16 + r) + J0 + 16 + i16];
+    }
+    const T* r0 = A + roff(J0 + i16) + 4 * g;        // rows J0 .. J0+15
+    const T* r1 = A + roff(J0 + 16 + i16) + 4 * g;   // rows J0+16 .. J0+31
+    v4<T> t00 = {0, 0, 0, 0}, t10 = t00, t11 = t00;
+    auto mma3 = [&](const v4<T>& a0, const v4<T>& a1) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            t00 = mfma(a0[st], a0[st], t00);
+            t10 = mfma(a1[st], a0[st], t10);
+            t11 = mfma(a1[st], a1[st], t11);
         }
+    };
+    const int nchunk = J0 / 16;   // even, >= 2
+    v4<T> p0 = load4(r0), p1 = load4(r1), q0, q1;
+    for (int ch = 0; ch < nchunk; ch += 2) {
+        q0 = load4(r0 + 16 * (ch + 1));
+        q1 = load4(r1 + 16 * (ch + 1));
+        mma3(p0, p1);
+        if (ch + 2 < nchunk) {
+            p0 = load4(r0 + 16 * (ch + 2));
+            p1 = load4(r1 + 16 * (ch + 2));
+        }
+        mma3(q0, q1);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = out_row<T>(g, v);
+        s.D[r][i16] = d00[v] - t00[v];
+        s.D[16 + r][i16] = d10[v] - t10[v];
+        s.D[16 + r][16 + i16] = d11[v] - t11[v];
+    }
+    __syncthreads();
+    const int f = factor_diag_block<T>(A, J0, s.D, &s.flag, lt_out + (size_t)slot * kNB * kNB);
+    if (f && lane == 0) {
+        status[c0 + slot] = f;
+        meta[slot].w = 0;
     }
 }
 
@@ -870,8 +862,9 @@ static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, T* scratch, int nsl
             for (int J = 0; J + kNB < a.np_max; J += kNB) {
                 const int tiles = (a.np_max - J - kNB + kRows2 - 1) / kRows2;
                 const int b = (J / kNB) & 1;
-                k_chol_step<T><<<pad * tiles, kTS, 0, st>>>(a, c0, J, pad, scratch, meta, status,
-                                                            lt_buf[b], lt_buf[b ^ 1]);
+                k_chol_step<T><<<pad * tiles, kTS, 0, st>>>(a, J, pad, scratch, meta, lt_buf[b]);
+                k_chol_diag<T><<<pad, kDT, 0, st>>>(a, c0, J + kNB, scratch, meta, status,
+                                                    lt_buf[b ^ 1]);
             }
             if (ncp > 0) {
                 k_z_forward<T><<<pad * ncp, kT2, 0, st>>>(a, c0, pad, scratch, meta, Z);
