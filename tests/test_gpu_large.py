@@ -1,0 +1,130 @@
+"""The large configurations on the GPU, through the C ABI (run with -m gpu).
+
+At these sizes the oracle cannot solve, so the solved weights are judged by
+two checks that hold at any size: the solver's true FP64 residual
+||f - A lambda|| / ||f|| (a full matvec on the GPU), and the GPU's A lambda
+itself, compared row by row with the oracle's sum on a random sample of rows
+(|y_gpu - y_oracle| <= 1e-13 (|A| |lambda|)_i, the FP64 matvec bar).  The
+oracle also gives f_i - (A lambda)_i on those rows, which must stay within the
+reported residual scale.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_0909_5413_amd as R
+from paper_0909_5413_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.lib()
+    return torch
+
+
+def solve(torch, w, d_pts, d_f, precision, rtol, max_iters=2000):
+    st = torch.cuda.current_stream()
+    lam = torch.empty(w.n, device="cuda", dtype=torch.float64)
+    h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, st)
+    try:
+        R.rbf_precond_setup(h, precision, st)
+        o = R.default_opts(rtol=rtol, precision=precision, stream=st, max_iters=max_iters)
+        info, status = R.rbf_solve_device(h, lam, o, ok=(R.RBF_OK, R.RBF_ENOCONV))
+        y = torch.empty_like(lam)
+        R.rbf_matvec_device(h, lam, y, R.RBF_FP64, R.RBF_ORDER_ORIGINAL, st)
+        torch.cuda.synchronize()
+    finally:
+        R.rbf_destroy(h)
+    return lam.cpu().numpy(), y.cpu().numpy(), info, status
+
+
+def sampled_rows(oracle_mod, pts, w, lam, y, f, nrows, seed):
+    """Oracle (A lam)_i and (|A| |lam|)_i on sampled rows i; returns the worst
+    matvec error relative to the bar and the sampled residual."""
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(pts.shape[0], nrows, replace=False)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff, w.overlap)
+    yo = P.evaluate(lam, pts[rows])
+    scale = P.evaluate(np.abs(lam), pts[rows])
+    err = np.max(np.abs(y[rows] - yo) / scale)
+    res = np.linalg.norm(f[rows] - yo) / np.linalg.norm(f[rows])
+    return err, res
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("name", ["c2_0.8", "c2_1.0"])
+def test_c2_fp64_and_mixed(torch_dev, oracle_mod, name):
+    torch = torch_dev
+    w = W.WORKLOADS[name]
+    pts = w.points()
+    f = w.values(pts)
+    d_pts = torch.tensor(pts, device="cuda")
+    d_f = torch.tensor(f, device="cuda")
+    for prec in (R.RBF_FP64, R.RBF_MIXED):
+        say(name, "precision", prec, "N", w.n)
+        lam, y, info, st = solve(torch, w, d_pts, d_f, prec, 1e-12)
+        assert st == R.RBF_OK, info.as_dict()
+        assert info.rel_residual <= 1.05e-12, info.as_dict()
+        # the GPU's own residual check, recomputed here from its matvec
+        assert np.linalg.norm(f - y) / np.linalg.norm(f) <= 1.05e-12
+        err, res = sampled_rows(oracle_mod, pts, w, lam, y, f, 2000, 11 + prec)
+        say(name, prec, "sampled matvec error / bar", err, "sampled residual", res)
+        assert err <= 1e-13, err
+        assert res <= 1e-10, res
+
+
+@pytest.mark.timeout(300)
+def test_c2_overlap_06_does_not_converge(torch_dev, oracle_mod):
+    """h/sigma = 0.6: the 6-sigma-truncated system is far too ill-conditioned
+    for GMRES(30) with this preconditioner; the oracle stalls the same way on a
+    small lattice of the same spacing.  Both forms report RBF_ENOCONV with a
+    finite best iterate."""
+    torch = torch_dev
+    w = W.WORKLOADS["c2_0.6"]
+    pts = w.points()
+    f = w.values(pts)
+    d_pts = torch.tensor(pts, device="cuda")
+    d_f = torch.tensor(f, device="cuda")
+    for prec in (R.RBF_FP64, R.RBF_MIXED):
+        say("c2_0.6 precision", prec)
+        lam, y, info, st = solve(torch, w, d_pts, d_f, prec, 1e-12, max_iters=120)
+        assert st == R.RBF_ENOCONV, info.as_dict()
+        assert np.all(np.isfinite(lam)) and np.isfinite(info.rel_residual)
+    sub = W.sub_lattice(w, 60)
+    sp = sub.points()
+    P = oracle_mod.Problem(sp, sub.sigma, sub.cutoff, sub.overlap)
+    _, oinfo = P.gmres(sub.values(sp), 30, 1e-12, max_iters=240, raise_on_error=False)
+    say("oracle on a 60x60 lattice at h/sigma 0.6:", oinfo.status, oinfo.rel_residual)
+    assert oinfo.rel_residual > 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_c4_fp64_1e14_and_mixed_1e12(torch_dev, oracle_mod):
+    """N = 50,013,184 (7072^2): mixed to 1e-12 first, then FP64 to 1e-14."""
+    torch = torch_dev
+    w = W.WORKLOADS["c4"]
+    pts = w.points()
+    f = w.values(pts)
+    d_pts = torch.tensor(pts, device="cuda")
+    d_f = torch.tensor(f, device="cuda")
+    for prec, rtol in ((R.RBF_MIXED, 1e-12), (R.RBF_FP64, 1e-14)):
+        say("c4 precision", prec, "rtol", rtol)
+        lam, y, info, st = solve(torch, w, d_pts, d_f, prec, rtol)
+        say("c4", prec, info.as_dict()["iterations"], info.rel_residual)
+        assert st == R.RBF_OK, info.as_dict()
+        assert info.rel_residual <= 1.05 * rtol, info.as_dict()
+        assert np.linalg.norm(f - y) / np.linalg.norm(f) <= 1.05 * rtol
+        err, res = sampled_rows(oracle_mod, pts, w, lam, y, f, 1000, 41 + prec)
+        say("c4", prec, "sampled matvec error / bar", err, "sampled residual", res)
+        assert err <= 1e-13, err
+        del lam, y
