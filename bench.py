@@ -48,6 +48,38 @@ def block_sizes(cell_start, ncx, ncy, overlap=1):
     return tot.ravel(), cnt.ravel()
 
 
+def step_kernel_flops(n_omega):
+    """Algorithmic FP64 flops of the factorisation-step launches for blocks of
+    n points: per 32-column block column J, the update of the rows below the
+    diagonal block (2 * 32 * J flops per row) and their solve against the
+    32x32 diagonal factor (32^2 flops per row)."""
+    import numpy as np
+    total = 0.0
+    for n in np.asarray(n_omega, dtype=np.int64):
+        J = np.arange(0, max(int(n) - 32, 0), 32, dtype=np.float64)
+        rows = n - J - 32
+        total += float(np.sum(rows * (64.0 * J + 1024.0)))
+    return total
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current source of that kernel (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_c1.md")
+    if not os.path.exists(path):
+        return None
+    for m in re.finditer(r"^traffic (\S+) bytes_per_launch=(\S+) source=(\S+) sha256=(\S+)$",
+                         open(path).read(), flags=re.M):
+        name, val, src, sha = m.groups()
+        if name != kernel:
+            continue
+        cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        return float(val) if cur == sha else None
+    return None
+
+
 def event_time(torch, stream, fn, reps):
     """Average milliseconds of fn() over reps launches, HIP events on stream."""
     start = torch.cuda.Event(enable_timing=True)
@@ -196,19 +228,37 @@ def main():
             "unit": "GB/s", "ms": t_ra, "bytes_per_launch": bytes_}
     finally:
         R.rbf_destroy(h)
+    # the setup's kernels one by one: HIP events the library records around
+    # each of its launches (profiling on), one FP64 setup
+    h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+    try:
+        R.rbf_set_profiling(h, True)
+        R.rbf_precond_setup(h, R.RBF_FP64, stream)
+        setup_k = R.rbf_setup_kernel_times(h, R.RBF_FP64)
+    finally:
+        R.rbf_destroy(h)
+    ms_cs, n_cs = setup_k["chol_step"]
+    sflops = step_kernel_flops(no)
+    kernels["chol_step64"] = {
+        "bound": "mfma", "achieved": sflops / (ms_cs * 1e-3) / 1e12,
+        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "ms": ms_cs / n_cs,
+        "launches": n_cs, "flops_per_launch": sflops / n_cs}
     for k in kernels.values():
         if "peak" in k:
             k["frac"] = k["achieved"] / k["peak"]
-    # the dominant kernel: the largest share of the FP64 step
+    # the dominant kernel: the single kernel with the largest share of the FP64
+    # step (all launches of it in one step)
     share = {
-        "precond_setup64": kernels["precond_setup64"]["ms"],
+        "chol_step64": ms_cs,
         "matvec64": kernels["matvec64"]["ms"] * last["matvecs64"],
         "rasm_apply64": kernels["rasm_apply64"]["ms"] * last["precond_applies"],
     }
-    dom = max(share, key=share.get)
+    share.update({f"setup_{k}": v[0] for k, v in setup_k.items() if k != "chol_step"})
+    dom = max((k for k in share if k in kernels and "peak" in kernels[k]), key=share.get)
     k = kernels[dom]
+    traffic = profiled_traffic(dom)
     roofline = {"kernel": dom, "bound": k["bound"], "achieved": k["achieved"], "peak": k["peak"],
-                "unit": k["unit"], "frac": k["frac"], "traffic": None,
+                "unit": k["unit"], "frac": k["frac"], "traffic": traffic,
                 "step_share_ms": share}
 
     # ---- mixed precision: time to the same tolerance ---------------------------
@@ -257,6 +307,7 @@ def main():
         "p99_latency_s": None,
         "roofline": roofline,
         "kernels": kernels,
+        "setup_kernels_ms": {k: {"ms": v[0], "launches": v[1]} for k, v in setup_k.items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -180,6 +180,28 @@ rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precisio
                              long long* members, double* z_rows, int* nomega,
                              int* ncentre);
 
+/* Kernels of the local factorisations (rbf_precond_setup), by kind. */
+typedef enum {
+    RBF_K_ASSEMBLE = 0,   /* local matrices and their first diagonal block */
+    RBF_K_CHOL_STEP = 1,  /* block-column update and panel solve, one launch per block column */
+    RBF_K_CHOL_DIAG = 2,  /* next diagonal block: product and 32x32 Cholesky */
+    RBF_K_FORWARD = 3,    /* forward solve L W = E_C on the trailing rows */
+    RBF_K_BACK = 4,       /* back solve L^T X = W, one launch per block row */
+    RBF_K_SETUP_KINDS = 5
+} rbf_setup_kernel;
+
+/* Event timing of the local factorisations.  With enable != 0, later
+ * rbf_precond_setup calls on this handle record a HIP event pair around every
+ * kernel launch they make (on their stream) and add up the elapsed time per
+ * kind; profiling costs two event records per launch.  rbf_setup_kernel_times
+ * gives, for the last profiled setup of the given precision, the total
+ * milliseconds ms[k] and launch count launches[k] of each kind k
+ * (RBF_K_SETUP_KINDS entries each, caller-owned host arrays).
+ * Errors: RBF_EINVAL (NULL argument), RBF_ESTATE (no profiled setup yet). */
+rbf_status rbf_set_profiling(rbf_problem* p, int enable);
+rbf_status rbf_setup_kernel_times(const rbf_problem* p, rbf_precision precision, double* ms,
+                                  int* launches);
+
 const char* rbf_status_string(rbf_status s);
 const char* rbf_last_error(void);   /* detail of the calling thread's last error */
 

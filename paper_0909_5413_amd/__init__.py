@@ -28,8 +28,12 @@ EXPORTED = [
     "rbf_precond_setup", "rbf_solve", "rbf_solve_device", "rbf_evaluate",
     "rbf_evaluate_device", "rbf_destroy", "rbf_grid", "rbf_binning",
     "rbf_neighbor_counts", "rbf_matvec_device", "rbf_precond_apply_device",
-    "rbf_precond_block", "rbf_status_string", "rbf_last_error",
+    "rbf_precond_block", "rbf_set_profiling", "rbf_setup_kernel_times", "rbf_status_string",
+    "rbf_last_error",
 ]
+RBF_K_ASSEMBLE, RBF_K_CHOL_STEP, RBF_K_CHOL_DIAG, RBF_K_FORWARD, RBF_K_BACK = range(5)
+RBF_K_SETUP_KINDS = 5
+SETUP_KERNELS = ["assemble", "chol_step", "chol_diag", "forward", "back"]
 
 
 class RbfLibraryMissing(RuntimeError):
@@ -97,6 +101,8 @@ def lib():
         "rbf_matvec_device": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
         "rbf_precond_apply_device": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
         "rbf_precond_block": (C.c_int, [vp, C.c_longlong, C.c_int, vp, vp, ip, ip]),
+        "rbf_set_profiling": (C.c_int, [vp, C.c_int]),
+        "rbf_setup_kernel_times": (C.c_int, [vp, C.c_int, dp, ip]),
         "rbf_status_string": (C.c_char_p, [C.c_int]),
         "rbf_last_error": (C.c_char_p, []),
     }
@@ -254,6 +260,18 @@ def rbf_precond_apply_device(h: int, d_v, d_z, precision: int = RBF_FP64,
                              order: int = RBF_ORDER_ORIGINAL, stream=None):
     _check(lib().rbf_precond_apply_device(h, _ptr(d_v), _ptr(d_z), precision, order,
                                           _stream(stream)), "rbf_precond_apply_device")
+
+
+def rbf_set_profiling(h: int, enable: bool = True):
+    _check(lib().rbf_set_profiling(h, 1 if enable else 0), "rbf_set_profiling")
+
+
+def rbf_setup_kernel_times(h: int, precision: int = RBF_FP64) -> dict:
+    """{kind: (total ms, launches)} of the last profiled rbf_precond_setup."""
+    ms = (C.c_double * RBF_K_SETUP_KINDS)()
+    n = (C.c_int * RBF_K_SETUP_KINDS)()
+    _check(lib().rbf_setup_kernel_times(h, precision, ms, n), "rbf_setup_kernel_times")
+    return {SETUP_KERNELS[k]: (ms[k], n[k]) for k in range(RBF_K_SETUP_KINDS)}
 
 
 def rbf_precond_block(h: int, cell: int, precision: int = RBF_FP64):

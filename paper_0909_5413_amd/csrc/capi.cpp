@@ -112,6 +112,10 @@ struct rbf_problem {
     double* lam = nullptr;             // last solution, sorted order
     bool solved = false;
     rbf::NeighborLists nl{};           // matvec neighbour lists (nunits == 0: none)
+    bool profiling = false;            // event timing of the setup launches
+    bool ktimes_valid[2] = {false, false};
+    double kms[2][RBF_K_SETUP_KINDS] = {};
+    int kcount[2][RBF_K_SETUP_KINDS] = {};
     std::vector<double> history;
 
     rbf_status alloc(void** out, size_t bytes_) {
@@ -474,19 +478,37 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
         return s;
     }
     rbf::PrecondArgs a = p->pc_args();
+    rbf::SetupProfile prof;
+    rbf::SetupProfile* pp = p->profiling ? &prof : nullptr;
     hipError_t e;
     if (is64)
         e = rbf::launch_precond_setup64(a, reinterpret_cast<double*>(Z),
                                         reinterpret_cast<double*>(scratch), (int)nslots, meta,
-                                        reinterpret_cast<double*>(lt), lvl, status, st);
+                                        reinterpret_cast<double*>(lt), lvl, status, st, pp);
     else
         e = rbf::launch_precond_setup32(a, reinterpret_cast<float*>(Z),
                                         reinterpret_cast<float*>(scratch), (int)nslots, meta,
-                                        reinterpret_cast<float*>(lt), lvl, status, st);
+                                        reinterpret_cast<float*>(lt), lvl, status, st, pp);
     std::vector<int> hs(nc);
     if (e == hipSuccess)
         e = hipMemcpyAsync(hs.data(), status, sizeof(int) * nc, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (pp) {
+        const int pi = is64 ? 0 : 1;
+        for (int k = 0; k < RBF_K_SETUP_KINDS; ++k) {
+            p->kms[pi][k] = 0.0;
+            p->kcount[pi][k] = 0;
+        }
+        for (auto& r : prof.recs) {
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+            p->kms[pi][r.kind] += ms;
+            p->kcount[pi][r.kind] += 1;
+            (void)hipEventDestroy(r.start);
+            (void)hipEventDestroy(r.stop);
+        }
+        p->ktimes_valid[pi] = e == hipSuccess;
+    }
     release_all();
     if (e != hipSuccess) {
         p->release(Z);
@@ -1192,6 +1214,26 @@ rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precisio
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_precond_block");
     }
+}
+
+rbf_status rbf_set_profiling(rbf_problem* p, int enable) {
+    if (!p) return fail(RBF_EINVAL, "NULL handle");
+    p->profiling = enable != 0;
+    return RBF_OK;
+}
+
+rbf_status rbf_setup_kernel_times(const rbf_problem* p, rbf_precision precision, double* ms,
+                                  int* launches) {
+    if (!p || !ms || !launches) return fail(RBF_EINVAL, "NULL argument");
+    if (precision != RBF_FP64 && precision != RBF_MIXED)
+        return fail(RBF_EINVAL, "unknown precision %d", (int)precision);
+    const int pi = precision == RBF_FP64 ? 0 : 1;
+    if (!p->ktimes_valid[pi]) return fail(RBF_ESTATE, "no profiled setup of this precision");
+    for (int k = 0; k < RBF_K_SETUP_KINDS; ++k) {
+        ms[k] = p->kms[pi][k];
+        launches[k] = p->kcount[pi][k];
+    }
+    return RBF_OK;
 }
 
 const char* rbf_status_string(rbf_status s) {

@@ -838,12 +838,28 @@ __global__ __launch_bounds__(kZT) void k_z_back(PrecondArgs a, long long c0, int
 // four times), which needs the batch's status on the host.
 template <typename T>
 static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, T* scratch, int nslots, int4* meta,
-                                 T* lt, int* lvl, int* status, hipStream_t st) {
+                                 T* lt, int* lvl, int* status, hipStream_t st,
+                                 SetupProfile* prof) {
     const int pad = (nslots + 7) / 8 * 8;
     const int ncp = (a.nc_max + kZCols - 1) / kZCols;
     T* lt_buf[2] = {lt, lt + (size_t)pad * kNB * kNB};
     const int attempts = sizeof(T) == 4 ? 5 : 1;
     std::vector<int> hs;
+    // every launch goes through here: with a profile, an event pair around it
+    hipError_t perr = hipSuccess;
+    auto timed = [&](int kind, auto&& launch) {
+        SetupProfile::Rec r{kind, nullptr, nullptr};
+        if (prof && perr == hipSuccess) {
+            perr = hipEventCreate(&r.start);
+            if (perr == hipSuccess) perr = hipEventCreate(&r.stop);
+            if (perr == hipSuccess) perr = hipEventRecord(r.start, st);
+        }
+        launch();
+        if (prof && perr == hipSuccess) {
+            perr = hipEventRecord(r.stop, st);
+            prof->recs.push_back(r);
+        }
+    };
     for (long long c0 = 0; c0 < a.ncells; c0 += nslots) {
         const int count = (int)(a.ncells - c0 < nslots ? a.ncells - c0 : nslots);
         for (int att = 0; att < attempts; ++att) {
@@ -857,33 +873,47 @@ static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, T* scratch, int nsl
                 for (int v : hs) any |= v > 0;
                 if (!any) break;
             }
-            k_setup_assemble<T><<<pad, kT2, 0, st>>>(a, c0, nslots, att > 0, scratch, meta, lvl,
-                                                     status, lt_buf[0]);
+            timed(RBF_K_ASSEMBLE, [&] {
+                k_setup_assemble<T><<<pad, kT2, 0, st>>>(a, c0, nslots, att > 0, scratch, meta,
+                                                         lvl, status, lt_buf[0]);
+            });
             for (int J = 0; J + kNB < a.np_max; J += kNB) {
                 const int tiles = (a.np_max - J - kNB + kRows2 - 1) / kRows2;
                 const int b = (J / kNB) & 1;
-                k_chol_step<T><<<pad * tiles, kTS, 0, st>>>(a, J, pad, scratch, meta, lt_buf[b]);
-                k_chol_diag<T><<<pad, kDT, 0, st>>>(a, c0, J + kNB, scratch, meta, status,
-                                                    lt_buf[b ^ 1]);
+                timed(RBF_K_CHOL_STEP, [&] {
+                    k_chol_step<T><<<pad * tiles, kTS, 0, st>>>(a, J, pad, scratch, meta,
+                                                                lt_buf[b]);
+                });
+                timed(RBF_K_CHOL_DIAG, [&] {
+                    k_chol_diag<T><<<pad, kDT, 0, st>>>(a, c0, J + kNB, scratch, meta, status,
+                                                        lt_buf[b ^ 1]);
+                });
             }
             if (ncp > 0) {
-                k_z_forward<T><<<pad * ncp, kT2, 0, st>>>(a, c0, pad, scratch, meta, Z);
+                timed(RBF_K_FORWARD, [&] {
+                    k_z_forward<T><<<pad * ncp, kT2, 0, st>>>(a, c0, pad, scratch, meta, Z);
+                });
                 for (int I = a.np_max / kNB - 1; I >= 0; --I)
-                    k_z_back<T><<<pad * ncp, kZT, 0, st>>>(a, c0, I, pad, scratch, meta, Z);
+                    timed(RBF_K_BACK, [&] {
+                        k_z_back<T><<<pad * ncp, kZT, 0, st>>>(a, c0, I, pad, scratch, meta, Z);
+                    });
             }
         }
     }
+    if (perr != hipSuccess) return perr;
     return hipGetLastError();
 }
 
 hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scratch, int nslots,
-                                  int4* meta, double* lt, int* lvl, int* status, hipStream_t st) {
-    return setup_lockstep<double>(a, Z, scratch, nslots, meta, lt, lvl, status, st);
+                                  int4* meta, double* lt, int* lvl, int* status, hipStream_t st,
+                                  SetupProfile* prof) {
+    return setup_lockstep<double>(a, Z, scratch, nslots, meta, lt, lvl, status, st, prof);
 }
 
 hipError_t launch_precond_setup32(const PrecondArgs& a, float* Z, float* scratch, int nslots,
-                                  int4* meta, float* lt, int* lvl, int* status, hipStream_t st) {
-    return setup_lockstep<float>(a, Z, scratch, nslots, meta, lt, lvl, status, st);
+                                  int4* meta, float* lt, int* lvl, int* status, hipStream_t st,
+                                  SetupProfile* prof) {
+    return setup_lockstep<float>(a, Z, scratch, nslots, meta, lt, lvl, status, st, prof);
 }
 
 namespace {

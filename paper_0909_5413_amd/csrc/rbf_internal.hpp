@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace rbf {
 
 struct Grid {
@@ -144,12 +146,22 @@ __host__ __device__ inline long long slot_elems64(int np_max) {
     const long long b = np_max / 32;
     return 512LL * b * (b + 1);
 }
+// Optional event timing of the setup launches: (kind, start, stop) per launch,
+// kinds as rbf_setup_kernel; the caller reads and destroys the events after
+// the stream has finished.
+struct SetupProfile {
+    struct Rec {
+        int kind;
+        hipEvent_t start, stop;
+    };
+    std::vector<Rec> recs;
+};
 hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scratch,
                                   int nslots, int4* meta, double* lt, int* lvl, int* status,
-                                  hipStream_t st);
+                                  hipStream_t st, SetupProfile* prof);
 hipError_t launch_precond_setup32(const PrecondArgs& a, float* Z, float* scratch,
                                   int nslots, int4* meta, float* lt, int* lvl, int* status,
-                                  hipStream_t st);
+                                  hipStream_t st, SetupProfile* prof);
 // z[own points of c] = Z_c v[members of c], every cell.
 hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const double* v,
                                double* z, hipStream_t st);

@@ -297,3 +297,27 @@ def test_error_codes(torch_dev):
         assert e.value.status == R.RBF_ENOMEM
     finally:
         R.rbf_destroy(h)
+
+
+def test_setup_kernel_times(problems):
+    """Event timing of the setup kernels: one assembly per batch, one step and
+    one diagonal launch per block column below the first, one forward solve,
+    one back solve per block row; all times positive."""
+    say("setup kernel times")
+    _, P, pts, f, sigma, cutoff = problems["c0"]
+    h = R.rbf_setup(pts, f, sigma, cutoff, 1)
+    try:
+        with pytest.raises(R.RbfError) as e:
+            R.rbf_setup_kernel_times(h, R.RBF_FP64)
+        assert e.value.status == R.RBF_ESTATE
+        R.rbf_set_profiling(h, True)
+        R.rbf_precond_setup(h, R.RBF_FP64)
+        kt = R.rbf_setup_kernel_times(h, R.RBF_FP64)
+    finally:
+        R.rbf_destroy(h)
+    ms = {k: v[0] for k, v in kt.items()}
+    n = {k: v[1] for k, v in kt.items()}
+    assert n["assemble"] >= 1 and n["forward"] == n["assemble"]
+    assert n["chol_step"] == n["chol_diag"] and n["chol_step"] % n["assemble"] == 0
+    assert n["back"] % n["assemble"] == 0 and n["back"] >= n["chol_step"]
+    assert all(v > 0 for v in ms.values()), ms
