@@ -10,8 +10,9 @@ all through the C ABI on device buffers.
 value = in-cutoff Gaussian interactions evaluated by the FP64 matvecs of the
 timed steps / timed seconds (the metric's unit, whole job).  The JSON line also
 carries the seconds to 1e-12 in FP64 and mixed precision, per-kernel rooflines
-(HIP events on the library's stream) and the CPU oracle timed on a bounded
-sample.
+(HIP events on the library's stream), the request loop's solves/s and p50/p99
+latency on the serving stream (FP64 and mixed), and the CPU oracle timed on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -80,6 +81,64 @@ def profiled_traffic(kernel):
     return None
 
 
+def serving_run(R, W, k, precision, max_active, max_iters):
+    """The request stream of the serving configuration through rbf_server_*:
+    a closed-loop run (all k requests submitted at once) measures the capacity
+    in solves/s, then an open-loop run submits the same requests at Poisson
+    arrival times with 0.7x that rate and records each request's latency
+    (submission to completion, the server's steady clock)."""
+    import numpy as np
+    reqs = W.serving_requests(k)
+    data = []
+    for w in reqs:
+        p = w.points()
+        data.append((w, p, w.values(p)))
+
+    def submit(srv, w, p, f):
+        return R.rbf_server_submit(srv, p, f, w.sigma, w.cutoff, w.overlap,
+                                   R.default_opts(rtol=w.rtol, precision=precision,
+                                                  max_iters=max_iters))
+
+    everything = tuple(range(11))
+    srv = R.rbf_server_create(max_active=max_active)
+    try:
+        t0 = time.perf_counter()
+        ids = [submit(srv, w, p, f) for w, p, f in data]
+        closed = [R.rbf_server_wait(srv, i, w.n, ok=everything) for (w, _, _), i in zip(data, ids)]
+        makespan = time.perf_counter() - t0
+    finally:
+        R.rbf_server_destroy(srv)
+    cap = k / makespan
+    rate = 0.7 * cap
+    arrivals = np.cumsum(np.random.default_rng(W.SEED_BASE * 1000 + 999).exponential(1.0 / rate, k))
+    srv = R.rbf_server_create(max_active=max_active)
+    try:
+        t0 = time.perf_counter()
+        ids = []
+        for (w, p, f), ta in zip(data, arrivals):
+            delay = t0 + ta - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(submit(srv, w, p, f))
+        opened = [R.rbf_server_wait(srv, i, w.n, ok=everything) for (w, _, _), i in zip(data, ids)]
+        span = time.perf_counter() - t0
+    finally:
+        R.rbf_server_destroy(srv)
+    lat = np.array([r.latency for _, r, _ in opened])
+    status = [st for _, _, st in opened]
+    return {
+        "requests": k, "precision": "fp64" if precision == R.RBF_FP64 else "mixed",
+        "max_active": max_active, "max_iters": max_iters,
+        "capacity_solves_per_s": cap, "offered_rate_per_s": rate,
+        "completed_solves_per_s": k / span,
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_mean_s": float(lat.mean()),
+        "ok": status.count(R.RBF_OK), "enoconv": status.count(R.RBF_ENOCONV),
+        "other": len(status) - status.count(R.RBF_OK) - status.count(R.RBF_ENOCONV),
+        "closed_loop_ok": sum(1 for _, _, st in closed if st == R.RBF_OK),
+    }
+
+
 def event_time(torch, stream, fn, reps):
     """Average milliseconds of fn() over reps launches, HIP events on stream."""
     start = torch.cuda.Event(enable_timing=True)
@@ -129,6 +188,11 @@ def main():
     ap.add_argument("--cpu-side", type=int, default=300, help="oracle sample lattice side")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=128,
+                    help="requests of the serving stream to run (the configuration has 512)")
+    ap.add_argument("--serve-active", type=int, default=8)
+    ap.add_argument("--serve-max-iters", type=int, default=300)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -282,6 +346,15 @@ def main():
                  "rel_residual": minfo.rel_residual, "weight_rel_diff_vs_fp64": werr}
         log("mixed", mixed)
 
+    serving = None
+    if not args.no_serve:
+        serving = {}
+        for tag, prec in (("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED)):
+            log("serving", tag, args.serve_requests, "requests")
+            serving[tag] = serving_run(R, W, args.serve_requests, prec, args.serve_active,
+                                       args.serve_max_iters)
+            log("serving", tag, serving[tag])
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: oracle on a", args.cpu_side, "lattice")
@@ -304,7 +377,8 @@ def main():
                                             "t_vecmdot", "t_other", "matvecs64",
                                             "precond_applies")},
         "mixed": mixed,
-        "p99_latency_s": None,
+        "p99_latency_s": serving["fp64"]["latency_p99_s"] if serving else None,
+        "serving": serving,
         "roofline": roofline,
         "kernels": kernels,
         "setup_kernels_ms": {k: {"ms": v[0], "launches": v[1]} for k, v in setup_k.items()},

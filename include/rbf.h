@@ -202,6 +202,58 @@ rbf_status rbf_set_profiling(rbf_problem* p, int enable);
 rbf_status rbf_setup_kernel_times(const rbf_problem* p, rbf_precision precision, double* ms,
                                   int* launches);
 
+/* ---- serving: a request loop over many problems (continuous batching) ---- */
+
+/* Requests are admitted in arrival order whenever fewer than max_active are
+ * on the device and their predicted device footprint fits what the budget has
+ * left (a request larger than the whole budget is admitted alone); each
+ * admitted request runs setup, preconditioner and solve on its own HIP stream
+ * from a worker thread, so requests that arrive while others run join as
+ * slots and memory free up and their kernels overlap on the device.  A
+ * request's launches are those of a lone rbf_solve_device call: its weights do
+ * not depend on the mix. */
+typedef struct rbf_server rbf_server;   /* opaque; created by rbf_server_create */
+
+typedef struct {
+    int max_active;            /* requests on the device at once, 1..64 (default 8) */
+    size_t max_device_bytes;   /* admission budget; 0 = 90% of the device memory free
+                                  at creation */
+} rbf_server_opts;
+
+typedef struct {
+    rbf_status status;         /* of the request's setup + preconditioner + solve */
+    rbf_solve_info info;       /* as rbf_solve_device fills it (history NULL) */
+    double t_queue;            /* seconds from submission to admission */
+    double t_run;              /* seconds from admission to completion */
+    double latency;            /* t_queue + t_run */
+    size_t predicted_bytes;    /* footprint charged against the budget */
+} rbf_request_result;
+
+void rbf_server_default_opts(rbf_server_opts* opts);
+/* Starts the dispatcher and max_active worker threads on the current device.
+ * Errors: RBF_EINVAL, RBF_ENOMEM, RBF_EDEVICE. */
+rbf_status rbf_server_create(const rbf_server_opts* opts, rbf_server** out);
+/* Queue one interpolation problem (arguments as rbf_setup, host arrays copied
+ * on the call, options as rbf_solve with their stream ignored); returns at
+ * once with the request's id.  Errors: RBF_EINVAL, RBF_ESTATE (server
+ * stopping). */
+rbf_status rbf_server_submit(rbf_server* s, const double* points, const double* values,
+                             long long n, double sigma, double cutoff, int overlap,
+                             const rbf_solve_opts* opts, long long* id);
+/* Block until request id has finished; copy its weights (n host doubles,
+ * original order; also on RBF_ENOCONV) to lambda_out if not NULL and its
+ * result to *result if not NULL.  Returns the request's status; each request
+ * is collected once (RBF_EINVAL for an unknown or collected id). */
+rbf_status rbf_server_wait(rbf_server* s, long long id, double* lambda_out,
+                           rbf_request_result* result);
+/* Counters: requests submitted and finished so far, on the device, queued, and
+ * the bytes their predicted footprints currently charge.  NULL fields skipped. */
+rbf_status rbf_server_stats(rbf_server* s, long long* submitted, long long* finished,
+                            int* active, int* queued, size_t* bytes_charged);
+/* Finish every submitted request, then stop the threads and free the server
+ * (uncollected results are dropped). */
+void rbf_server_destroy(rbf_server* s);
+
 const char* rbf_status_string(rbf_status s);
 const char* rbf_last_error(void);   /* detail of the calling thread's last error */
 

@@ -28,8 +28,9 @@ EXPORTED = [
     "rbf_precond_setup", "rbf_solve", "rbf_solve_device", "rbf_evaluate",
     "rbf_evaluate_device", "rbf_destroy", "rbf_grid", "rbf_binning",
     "rbf_neighbor_counts", "rbf_matvec_device", "rbf_precond_apply_device",
-    "rbf_precond_block", "rbf_set_profiling", "rbf_setup_kernel_times", "rbf_status_string",
-    "rbf_last_error",
+    "rbf_precond_block", "rbf_set_profiling", "rbf_setup_kernel_times",
+    "rbf_server_default_opts", "rbf_server_create", "rbf_server_submit", "rbf_server_wait",
+    "rbf_server_stats", "rbf_server_destroy", "rbf_status_string", "rbf_last_error",
 ]
 RBF_K_ASSEMBLE, RBF_K_CHOL_STEP, RBF_K_CHOL_DIAG, RBF_K_FORWARD, RBF_K_BACK = range(5)
 RBF_K_SETUP_KINDS = 5
@@ -71,6 +72,16 @@ class SolveInfo(C.Structure):
 _lib = None
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("max_active", C.c_int), ("max_device_bytes", C.c_size_t)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("info", SolveInfo), ("t_queue", C.c_double),
+                ("t_run", C.c_double), ("latency", C.c_double),
+                ("predicted_bytes", C.c_size_t)]
+
+
 def lib():
     """The loaded C library (raises RbfLibraryMissing if it was never built)."""
     global _lib
@@ -102,6 +113,13 @@ def lib():
         "rbf_precond_apply_device": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
         "rbf_precond_block": (C.c_int, [vp, C.c_longlong, C.c_int, vp, vp, ip, ip]),
         "rbf_set_profiling": (C.c_int, [vp, C.c_int]),
+        "rbf_server_default_opts": (None, [C.POINTER(ServerOpts)]),
+        "rbf_server_create": (C.c_int, [C.POINTER(ServerOpts), pp]),
+        "rbf_server_submit": (C.c_int, [vp, vp, vp, C.c_longlong, C.c_double, C.c_double, C.c_int,
+                                        C.POINTER(SolveOpts), lp]),
+        "rbf_server_wait": (C.c_int, [vp, C.c_longlong, vp, C.POINTER(RequestResult)]),
+        "rbf_server_stats": (C.c_int, [vp, lp, lp, ip, ip, C.POINTER(C.c_size_t)]),
+        "rbf_server_destroy": (None, [vp]),
         "rbf_setup_kernel_times": (C.c_int, [vp, C.c_int, dp, ip]),
         "rbf_status_string": (C.c_char_p, [C.c_int]),
         "rbf_last_error": (C.c_char_p, []),
@@ -272,6 +290,52 @@ def rbf_setup_kernel_times(h: int, precision: int = RBF_FP64) -> dict:
     n = (C.c_int * RBF_K_SETUP_KINDS)()
     _check(lib().rbf_setup_kernel_times(h, precision, ms, n), "rbf_setup_kernel_times")
     return {SETUP_KERNELS[k]: (ms[k], n[k]) for k in range(RBF_K_SETUP_KINDS)}
+
+
+def rbf_server_create(max_active: int = 8, max_device_bytes: int = 0) -> int:
+    o = ServerOpts()
+    lib().rbf_server_default_opts(C.byref(o))
+    o.max_active = max_active
+    o.max_device_bytes = max_device_bytes
+    h = C.c_void_p()
+    _check(lib().rbf_server_create(C.byref(o), C.byref(h)), "rbf_server_create")
+    return h.value
+
+
+def rbf_server_submit(srv: int, points, values, sigma: float, cutoff: float, overlap: int = 1,
+                      opts: SolveOpts | None = None) -> int:
+    pts = _host(points).reshape(-1, 2)
+    vals = _host(values)
+    rid = C.c_longlong()
+    _check(lib().rbf_server_submit(srv, _ptr(pts), _ptr(vals), pts.shape[0], sigma, cutoff,
+                                   overlap, C.byref(opts) if opts is not None else None,
+                                   C.byref(rid)), "rbf_server_submit")
+    return rid.value
+
+
+def rbf_server_wait(srv: int, rid: int, n: int, ok=(RBF_OK, RBF_ENOCONV)):
+    """(lambda (original order) or None, RequestResult, status)."""
+    lam = np.empty(n)
+    res = RequestResult()
+    st = lib().rbf_server_wait(srv, rid, _ptr(lam), C.byref(res))
+    if st not in ok:
+        raise RbfError(st, "rbf_server_wait", last_error())
+    return (lam if st in (RBF_OK, RBF_ENOCONV) else None), res, st
+
+
+def rbf_server_stats(srv: int) -> dict:
+    sub, fin = C.c_longlong(), C.c_longlong()
+    act, que = C.c_int(), C.c_int()
+    b = C.c_size_t()
+    _check(lib().rbf_server_stats(srv, C.byref(sub), C.byref(fin), C.byref(act), C.byref(que),
+                                  C.byref(b)), "rbf_server_stats")
+    return {"submitted": sub.value, "finished": fin.value, "active": act.value,
+            "queued": que.value, "bytes_charged": b.value}
+
+
+def rbf_server_destroy(srv: int):
+    if srv:
+        lib().rbf_server_destroy(srv)
 
 
 def rbf_precond_block(h: int, cell: int, precision: int = RBF_FP64):

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librbf_hip.so")
 OBJ = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["binning.hip", "matvec.hip", "precond.hip", "krylov.hip", "capi.cpp"]
+SOURCES = ["binning.hip", "matvec.hip", "precond.hip", "krylov.hip", "capi.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RBF_OFFLOAD_ARCH", "gfx950")
@@ -47,11 +47,11 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 5) -> str:
+def build(jobs: int = 6) -> str:
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -119,3 +119,21 @@ def sub_lattice(w: Workload, n_side: int) -> Workload:
     """A smaller lattice with the same spacing ratio, jitter and cutoff rule."""
     return Workload(f"{w.name}_sub{n_side}", n_side, w.h_over_sigma, w.jitter, w.r0,
                     w.rtol, w.seed, w.cutoff_sigmas, w.overlap)
+
+
+def serving_requests(k: int, seed_base: int = SEED_BASE * 1000, n_lo: float = 1e3,
+                     n_hi: float = 1e6, hs_lo: float = 0.6, hs_hi: float = 1.0,
+                     r0_lo: float = 0.1, r0_hi: float = 0.4, rtol: float = 1e-12) -> list:
+    """A stream of k interpolation requests: request i draws, from
+    default_rng(seed_base + i), N log-uniform in [n_lo, n_hi] (n_side =
+    round(sqrt(N))), h/sigma uniform in [hs_lo, hs_hi] and the data's core
+    radius r0 uniform in [r0_lo, r0_hi]; its points use the same seed."""
+    out = []
+    for i in range(k):
+        rng = np.random.default_rng(seed_base + i)
+        n = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        hs = float(rng.uniform(hs_lo, hs_hi))
+        r0 = float(rng.uniform(r0_lo, r0_hi))
+        side = max(int(round(np.sqrt(n))), 4)
+        out.append(Workload(f"req{i}", side, hs, r0=r0, rtol=rtol, seed=seed_base + i))
+    return out

@@ -1,0 +1,120 @@
+"""The request loop (rbf_server_*) on the GPU, through the C ABI (-m gpu).
+
+Isolation: every request's weights from a mix of concurrent requests equal,
+bit for bit, the weights of the same request solved alone on a fresh handle
+(the server runs each request's launches unchanged on its own stream).
+Admission: with a budget that fits about two requests the server still
+finishes every request, never charges more than the budget plus one request,
+and releases everything at the end.  A failing request does not disturb the
+others.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import paper_0909_5413_amd as R
+from paper_0909_5413_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.lib()
+    return torch
+
+
+def mix(k, seed_base):
+    reqs = W.serving_requests(k, seed_base=seed_base, n_lo=2e3, n_hi=6e4, hs_lo=0.75)
+    out = []
+    for i, w in enumerate(reqs):
+        pts = w.points()
+        out.append((w, pts, w.values(pts), R.RBF_FP64 if i % 2 == 0 else R.RBF_MIXED))
+    return out
+
+
+def alone(w, pts, f, prec):
+    h = R.rbf_setup(pts, f, w.sigma, w.cutoff, w.overlap)
+    try:
+        lam, info, st = R.rbf_solve(h, w.n, R.default_opts(rtol=w.rtol, precision=prec),
+                                    ok=(R.RBF_OK, R.RBF_ENOCONV))
+    finally:
+        R.rbf_destroy(h)
+    return lam, st
+
+
+def test_mix_equals_alone(torch_dev):
+    reqs = mix(8, 777000)
+    ref = []
+    for w, pts, f, prec in reqs:
+        say("alone", w.name, w.n, w.h_over_sigma, prec)
+        ref.append(alone(w, pts, f, prec))
+    srv = R.rbf_server_create(max_active=4)
+    try:
+        ids = [R.rbf_server_submit(srv, pts, f, w.sigma, w.cutoff, w.overlap,
+                                   R.default_opts(rtol=w.rtol, precision=prec))
+               for w, pts, f, prec in reqs]
+        for (w, pts, f, prec), rid, (lam0, st0) in zip(reqs, ids, ref):
+            lam, res, st = R.rbf_server_wait(srv, rid, w.n)
+            say("mixed-in", w.name, R.status_name(st), res.latency, res.info.iterations)
+            assert st == st0
+            assert np.array_equal(lam, lam0)
+        stats = R.rbf_server_stats(srv)
+        assert stats["finished"] == len(reqs) and stats["active"] == 0
+        assert stats["bytes_charged"] == 0
+    finally:
+        R.rbf_server_destroy(srv)
+
+
+def test_admission_budget_and_failures(torch_dev):
+    reqs = mix(6, 888000)
+    # one request with two identical points: fails alone, the others are unaffected
+    w, pts, f, prec = reqs[2]
+    bad = pts.copy()
+    bad[5] = bad[9]
+    reqs[2] = (w, bad, f, prec)
+    srv0 = R.rbf_server_create(max_active=1)
+    try:
+        sizes = []
+        for w, pts, f, prec in reqs:
+            rid = R.rbf_server_submit(srv0, pts, f, w.sigma, w.cutoff, w.overlap,
+                                      R.default_opts(rtol=w.rtol, precision=prec))
+            _, res, _ = R.rbf_server_wait(srv0, rid, w.n, ok=tuple(range(11)))
+            sizes.append(res.predicted_bytes)
+    finally:
+        R.rbf_server_destroy(srv0)
+    budget = int(2.2 * max(sizes))
+    srv = R.rbf_server_create(max_active=8, max_device_bytes=budget)
+    try:
+        ids = [R.rbf_server_submit(srv, pts, f, w.sigma, w.cutoff, w.overlap,
+                                   R.default_opts(rtol=w.rtol, precision=prec))
+               for w, pts, f, prec in reqs]
+        peak = 0
+        while True:
+            s = R.rbf_server_stats(srv)
+            peak = max(peak, s["bytes_charged"])
+            if s["finished"] == len(reqs):
+                break
+            time.sleep(0.002)
+        assert peak <= budget + max(sizes)
+        for i, ((w, pts, f, prec), rid) in enumerate(zip(reqs, ids)):
+            lam, res, st = R.rbf_server_wait(srv, rid, w.n, ok=tuple(range(11)))
+            say("budgeted", w.name, R.status_name(st))
+            if i == 2:
+                assert st == R.RBF_EDUPLICATE
+            else:
+                assert st == R.RBF_OK
+                lam0, st0 = alone(w, pts, f, prec)
+                assert np.array_equal(lam, lam0)
+        assert R.rbf_server_stats(srv)["bytes_charged"] == 0
+    finally:
+        R.rbf_server_destroy(srv)
