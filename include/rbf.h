@@ -143,8 +143,25 @@ rbf_status rbf_evaluate(const rbf_problem* p, const double* targets, long long m
 rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, long long m,
                                double* d_out, void* stream);
 
-/* Release everything the handle owns (NULL is ignored). */
+/* Release everything the handle owns (NULL is ignored).  Waits for the work
+ * that the handle's calls enqueued, on whatever stream, and no other work; the
+ * handle's device buffers go to the library's block cache (below). */
 void rbf_destroy(rbf_problem* p);
+
+/* Device block cache.  Buffers a handle gives back (on rbf_destroy, or
+ * scratch freed inside a call) are kept by the library and handed to later
+ * allocations of about the same size on the same device (a block at most
+ * 1/8 larger than asked), so that a stream of problems of varying sizes
+ * neither maps fresh memory per call nor waits for the whole device on each
+ * free.  A block is handed out again only after the work that last used it
+ * has finished.  Idle blocks are returned to the runtime when an allocation
+ * fails, when they exceed a quarter of the device memory, or here.
+ *   device      device ordinal, or -1 for every device
+ *   trim        non-zero: return the idle blocks of `device` to the runtime
+ *   idle_bytes  out (may be NULL): idle bytes held before trimming
+ * Thread-safe.  Budgets (max_device_bytes) count the block sizes actually
+ * held, which are rounded up to 2 MiB (powers of two below 1 MiB). */
+rbf_status rbf_block_cache(int device, int trim, size_t* idle_bytes);
 
 /* ---- single steps of the method, for measurement and parity checks -------- */
 

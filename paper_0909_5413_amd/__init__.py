@@ -26,7 +26,7 @@ RBF_MAX_CELL_POINTS = 1536
 EXPORTED = [
     "rbf_default_opts", "rbf_setup", "rbf_setup_device", "rbf_set_values",
     "rbf_precond_setup", "rbf_solve", "rbf_solve_device", "rbf_evaluate",
-    "rbf_evaluate_device", "rbf_destroy", "rbf_grid", "rbf_binning",
+    "rbf_evaluate_device", "rbf_destroy", "rbf_block_cache", "rbf_grid", "rbf_binning",
     "rbf_neighbor_counts", "rbf_matvec_device", "rbf_precond_apply_device",
     "rbf_precond_block", "rbf_set_profiling", "rbf_setup_kernel_times",
     "rbf_server_default_opts", "rbf_server_create", "rbf_server_submit", "rbf_server_wait",
@@ -106,6 +106,7 @@ def lib():
         "rbf_evaluate": (C.c_int, [vp, vp, C.c_longlong, vp]),
         "rbf_evaluate_device": (C.c_int, [vp, vp, C.c_longlong, vp, vp]),
         "rbf_destroy": (None, [vp]),
+        "rbf_block_cache": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
         "rbf_grid": (C.c_int, [vp, dp, lp]),
         "rbf_binning": (C.c_int, [vp, vp, vp, vp]),
         "rbf_neighbor_counts": (C.c_int, [vp, vp, lp]),
@@ -243,6 +244,14 @@ def rbf_evaluate_device(h: int, d_targets, m: int, d_out, stream=None):
 def rbf_destroy(h: int):
     if h:
         lib().rbf_destroy(h)
+
+
+def rbf_block_cache(device: int = -1, trim: bool = False) -> int:
+    """Idle bytes held by the library's device block cache (before trimming);
+    trim=True returns them to the runtime."""
+    b = C.c_size_t()
+    _check(lib().rbf_block_cache(device, 1 if trim else 0, C.byref(b)), "rbf_block_cache")
+    return b.value
 
 
 def rbf_grid(h: int):

@@ -15,6 +15,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -65,6 +67,176 @@ struct Timer {
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+};
+
+// Device blocks released by problems, kept for reuse by later allocations of
+// about the same size.  A fresh multi-GB hipMalloc maps new pages and hipFree
+// waits for the whole device, which together cost more than a solve when
+// problems of varying sizes follow one another (the serving loop).  A block
+// released while work may still use it carries an event recorded on that
+// work's stream; the next owner waits for the event before the block is
+// handed out.  Idle blocks are returned to the runtime when an allocation
+// fails, when they exceed a quarter of the device memory, or on
+// rbf_trim_cache.
+class BlockCache {
+public:
+    static BlockCache& get() {
+        static BlockCache* c = new BlockCache;  // outlives every static destructor
+        return *c;
+    }
+    // Sizes are rounded so that blocks of one size class are interchangeable.
+    static size_t round(size_t b) {
+        if (b <= 256) return 256;
+        if (b < (1u << 20)) {
+            size_t r = 256;
+            while (r < b) r <<= 1;
+            return r;
+        }
+        const size_t g = 2u << 20;
+        return (b + g - 1) / g * g;
+    }
+    // A block of at least `want` (rounded) and at most `limit` bytes; *got is
+    // its size.
+    hipError_t alloc(int dev, size_t want, size_t limit, void** out, size_t* got) {
+        const size_t r = round(want);
+        const size_t hi = std::min(limit, r + r / 8);
+        Blk b{};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (auto it = idle_.lower_bound(r); it != idle_.end() && it->first <= hi; ++it)
+                if (it->second.dev == dev) {
+                    b = it->second;
+                    idle_.erase(it);
+                    idle_bytes_[dev] -= b.bytes;
+                    found = true;
+                    break;
+                }
+        }
+        if (found) {
+            hipError_t e = settle(b);
+            if (e != hipSuccess) {
+                (void)hipFree(b.p);
+                return e;
+            }
+            *out = b.p;
+            *got = b.bytes;
+            return hipSuccess;
+        }
+        if (r > limit) return hipErrorOutOfMemory;
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, r);
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            trim(dev);
+            e = hipMalloc(&p, r);
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        *out = p;
+        *got = r;
+        return hipSuccess;
+    }
+    // Takes back a block; work enqueued on `st` before this call may still use it.
+    void put(int dev, void* p, size_t bytes, hipStream_t st, bool pending) {
+        Blk b{p, bytes, dev, nullptr};
+        if (pending) {
+            if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+                b.ev = nullptr;
+                (void)hipStreamSynchronize(st);
+            } else if (hipEventRecord(b.ev, st) != hipSuccess) {
+                (void)hipEventDestroy(b.ev);
+                b.ev = nullptr;
+                (void)hipStreamSynchronize(st);
+            }
+        }
+        std::vector<Blk> evict;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            idle_.emplace(bytes, b);
+            idle_bytes_[dev] += bytes;
+            const size_t cap = cap_locked(dev);
+            // evict the largest idle blocks of the device beyond the cap
+            for (auto it = idle_.end(); idle_bytes_[dev] > cap && it != idle_.begin();) {
+                --it;
+                if (it->second.dev != dev) continue;
+                idle_bytes_[dev] -= it->second.bytes;
+                evict.push_back(it->second);
+                it = idle_.erase(it);
+            }
+        }
+        for (Blk& e : evict) {
+            (void)settle(e);
+            (void)hipFree(e.p);
+        }
+    }
+    // Returns the idle blocks of device dev (all devices if dev < 0) to the
+    // runtime; the number of bytes freed.
+    size_t trim(int dev) {
+        std::vector<Blk> evict;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (auto it = idle_.begin(); it != idle_.end();) {
+                if (dev < 0 || it->second.dev == dev) {
+                    idle_bytes_[it->second.dev] -= it->second.bytes;
+                    evict.push_back(it->second);
+                    it = idle_.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        size_t freed = 0;
+        for (Blk& e : evict) {
+            (void)settle(e);
+            (void)hipFree(e.p);
+            freed += e.bytes;
+        }
+        return freed;
+    }
+    size_t idle_bytes(int dev) {
+        std::lock_guard<std::mutex> lk(mu_);
+        size_t t = 0;
+        for (auto& kv : idle_bytes_)
+            if (dev < 0 || kv.first == dev) t += kv.second;
+        return t;
+    }
+
+private:
+    struct Blk {
+        void* p;
+        size_t bytes;
+        int dev;
+        hipEvent_t ev;     // completion of the last work that used the block, or NULL
+    };
+    static hipError_t settle(Blk& b) {
+        hipError_t e = hipSuccess;
+        if (b.ev) {
+            e = hipEventSynchronize(b.ev);
+            (void)hipEventDestroy(b.ev);
+            b.ev = nullptr;
+        }
+        return e;
+    }
+    size_t cap_locked(int dev) {
+        auto it = cap_.find(dev);
+        if (it != cap_.end()) return it->second;
+        size_t fr = 0, tot = 0;
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(dev);
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = 0;
+        (void)hipSetDevice(cur);
+        const size_t cap = tot / 4;
+        cap_[dev] = cap;
+        return cap;
+    }
+    std::mutex mu_;
+    std::multimap<size_t, Blk> idle_;
+    std::map<int, size_t> idle_bytes_;
+    std::map<int, size_t> cap_;
 };
 
 }  // namespace
@@ -119,15 +291,19 @@ struct rbf_problem {
     std::vector<double> history;
 
     rbf_status alloc(void** out, size_t bytes_) {
-        if (budget && this->bytes + bytes_ > budget)
+        const size_t want = BlockCache::round(bytes_);
+        if (budget && this->bytes + want > budget)
             return fail(RBF_ENOMEM, "device memory budget of %zu bytes exceeded (%zu + %zu)",
-                        budget, this->bytes, bytes_);
+                        budget, this->bytes, want);
+        const size_t limit = budget ? budget - this->bytes : (size_t)-1;
         void* p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes_ ? bytes_ : 1);
+        size_t got = 0;
+        hipError_t e = BlockCache::get().alloc(device, bytes_, limit, &p, &got);
         if (e != hipSuccess)
-            return fail(RBF_ENOMEM, "hipMalloc(%zu): %s", bytes_, hipGetErrorString(e));
-        bufs.push_back({p, bytes_});
-        this->bytes += bytes_;
+            return fail(RBF_ENOMEM, "device allocation of %zu bytes: %s", want,
+                        hipGetErrorString(e));
+        bufs.push_back({p, got});
+        this->bytes += got;
         *out = p;
         return RBF_OK;
     }
@@ -135,17 +311,33 @@ struct rbf_problem {
     rbf_status alloc_n(T** out, long long count) {
         return alloc(reinterpret_cast<void**>(out), sizeof(T) * (size_t)(count > 0 ? count : 1));
     }
-    void release(void* p) {
+    // Gives a buffer back; work enqueued on st before this call may still use it.
+    void release(void* q, hipStream_t st) {
         for (size_t i = 0; i < bufs.size(); ++i)
-            if (bufs[i].p == p) {
-                (void)hipFree(p);
+            if (bufs[i].p == q) {
+                BlockCache::get().put(device, q, bufs[i].bytes, st, true);
                 bytes -= bufs[i].bytes;
                 bufs.erase(bufs.begin() + i);
                 return;
             }
     }
+    // Records the completion of the work a call enqueued on st, so that
+    // destruction waits for it and no longer.
+    void mark(hipStream_t st) const {
+        if (!done && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+            done = nullptr;
+            (void)hipStreamSynchronize(st);
+            return;
+        }
+        if (hipEventRecord(done, st) != hipSuccess) (void)hipStreamSynchronize(st);
+    }
+    mutable hipEvent_t done = nullptr;
     ~rbf_problem() {
-        for (auto& b : bufs) (void)hipFree(b.p);
+        if (done) {
+            (void)hipEventSynchronize(done);
+            (void)hipEventDestroy(done);
+        }
+        for (auto& b : bufs) BlockCache::get().put(device, b.p, b.bytes, nullptr, false);
     }
 
     rbf::MatvecArgs mv_args() const {
@@ -193,9 +385,28 @@ struct rbf_problem {
     }
 };
 
+namespace rbf {
+hipError_t cached_alloc(int dev, size_t bytes, void** out, size_t* got) {
+    return BlockCache::get().alloc(dev, bytes, (size_t)-1, out, got);
+}
+void cached_free(int dev, void* p, size_t bytes, hipStream_t st) {
+    BlockCache::get().put(dev, p, bytes, st, true);
+}
+}  // namespace rbf
+
 namespace {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Marks, when a call returns (also on errors), the end of the work it
+// enqueued on its stream.
+struct MarkOnExit {
+    const rbf_problem* p;
+    hipStream_t st;
+    ~MarkOnExit() {
+        if (p) p->mark(st);
+    }
+};
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -253,7 +464,7 @@ rbf_status build_lists(rbf_problem* p, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(off, ho.data(), sizeof(long long) * (nu + 1), hipMemcpyHostToDevice, st));
     HIP_TRY(rbf::launch_list_fill(a, unit, nu, off, len, idx, st));
     HIP_TRY(hipStreamSynchronize(st));
-    p->release(nbv);
+    p->release(nbv, st);
     p->nl.unit = unit;
     p->nl.off = off;
     p->nl.len = len;
@@ -329,11 +540,11 @@ rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals,
                     RBF_MAX_CELL_POINTS);
     if (h_flags[2]) return fail(RBF_EDUPLICATE, "two points are bit-identical");
     p->have_values = d_vals != nullptr;
-    p->release(counts);
-    p->release(slot);
-    p->release(tmp);
-    p->release(scan_work);
-    p->release(work);
+    p->release(counts, st);
+    p->release(slot, st);
+    p->release(tmp, st);
+    p->release(scan_work, st);
+    p->release(work, st);
     // keep `bad` as a flag word for later use
     p->flag = bad;
 
@@ -409,13 +620,15 @@ rbf_status create(const double* pts, const double* vals, bool on_device, long lo
             if (e != hipSuccess) s = fail(RBF_EDEVICE, "copy to device: %s", hipGetErrorString(e));
         }
         if (s == RBF_OK) s = setup_impl(p, dp, dv, st);
-        if (dp) p->release(dp);
-        if (dv) p->release(dv);
+        if (dp) p->release(dp, st);
+        if (dv) p->release(dv, st);
     }
     if (s != RBF_OK) {
+        p->mark(st);
         delete p;
         return s;
     }
+    p->mark(st);
     *out = p;
     return RBF_OK;
 }
@@ -466,14 +679,14 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     if (s == RBF_OK) s = p->alloc_n(&lvl, pad);
     if (s == RBF_OK) s = p->alloc_n(&lt, 2 * pad * 1024);
     auto release_all = [&]() {
-        if (scratch) p->release(scratch);
-        if (status) p->release(status);
-        if (meta) p->release(meta);
-        if (lvl) p->release(lvl);
-        if (lt) p->release(lt);
+        if (scratch) p->release(scratch, st);
+        if (status) p->release(status, st);
+        if (meta) p->release(meta, st);
+        if (lvl) p->release(lvl, st);
+        if (lt) p->release(lt, st);
     };
     if (s != RBF_OK) {
-        p->release(Z);
+        p->release(Z, st);
         release_all();
         return s;
     }
@@ -511,7 +724,7 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     }
     release_all();
     if (e != hipSuccess) {
-        p->release(Z);
+        p->release(Z, st);
         return fail(RBF_EDEVICE, "preconditioner setup: %s", hipGetErrorString(e));
     }
     int bad = 0, shifted = 0;
@@ -525,7 +738,7 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
         }
     }
     if (bad) {
-        p->release(Z);
+        p->release(Z, st);
         return fail(RBF_ENOTPD, "%d local blocks are not positive definite (first: cell %lld, pivot %d)",
                     bad, first_bad, hs[first_bad]);
     }
@@ -572,10 +785,10 @@ rbf_status rasm(rbf_problem* p, rbf_precision prec, const double* v, double* z, 
     return RBF_OK;
 }
 
-rbf_status ensure_workspace(rbf_problem* p, int m) {
+rbf_status ensure_workspace(rbf_problem* p, int m, hipStream_t st) {
     if (p->ws_m >= m) return RBF_OK;
     if (p->V) {
-        p->release(p->V);
+        p->release(p->V, st);
         p->V = nullptr;
     }
     const long long n = p->n;
@@ -770,7 +983,7 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
         t_pc = t.sec();
     }
     const int m = opts.restart;
-    RBF_TRY(ensure_workspace(p, m));
+    RBF_TRY(ensure_workspace(p, m, st));
 
     const long long n = p->n;
     // initial guess (sorted order)
@@ -891,8 +1104,8 @@ rbf_status count_interactions(rbf_problem* p, int* d_nnb_sorted, hipStream_t st)
     HIP_TRY(hipMemcpyAsync(&h, tot, sizeof h, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     p->interactions = h;
-    p->release(y);
-    p->release(tot);
+    p->release(y, st);
+    p->release(tot, st);
     return RBF_OK;
 }
 
@@ -940,7 +1153,7 @@ rbf_status evaluate_impl(const rbf_problem* cp, const double* d_t, long long m, 
     for (void* q : {(void*)work, (void*)flag, (void*)cell_of, (void*)slot, (void*)counts, (void*)tcs,
                     (void*)tperm, (void*)scan_work, (void*)tx, (void*)ty, (void*)yo, (void*)fx,
                     (void*)fy})
-        p->release(q);
+        p->release(q, st);
     if (hflag) return fail(RBF_EINVAL, "targets contain NaN or Inf");
     return RBF_OK;
 }
@@ -983,6 +1196,7 @@ rbf_status rbf_setup_device(const double* d_points, const double* d_values, long
 rbf_status rbf_set_values(rbf_problem* p, const double* values, int on_device, void* stream) {
     if (!p || !values) return fail(RBF_EINVAL, "NULL argument");
     hipStream_t st = as_stream(stream);
+    MarkOnExit mk{p, st};
     double* src = const_cast<double*>(values);
     double* tmp = nullptr;
     if (!on_device) {
@@ -997,7 +1211,7 @@ rbf_status rbf_set_values(rbf_problem* p, const double* values, int on_device, v
     int h = 0;
     HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (tmp) p->release(tmp);
+    if (tmp) p->release(tmp, st);
     if (h) return fail(RBF_EINVAL, "values contain NaN or Inf");
     p->have_values = true;
     p->solved = false;
@@ -1007,6 +1221,7 @@ rbf_status rbf_set_values(rbf_problem* p, const double* values, int on_device, v
 rbf_status rbf_precond_setup(rbf_problem* p, rbf_precision precision, void* stream) {
     if (!p) return fail(RBF_EINVAL, "NULL problem");
     try {
+        MarkOnExit mk{p, as_stream(stream)};
         return precond_setup(p, precision, as_stream(stream));
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_precond_setup");
@@ -1017,6 +1232,7 @@ rbf_status rbf_solve(rbf_problem* p, const rbf_solve_opts* opts, const double* l
                      double* lambda_out, rbf_solve_info* info) {
     if (!p || !lambda_out) return fail(RBF_EINVAL, "NULL argument");
     try {
+        MarkOnExit mk{p, as_stream(opts ? opts->stream : nullptr)};
         rbf_status s = solve_impl(p, opts, nullptr, false, lambda0, info);
         if (s != RBF_OK && s != RBF_ENOCONV && s != RBF_EBREAKDOWN) return s;
         hipStream_t st = as_stream(opts ? opts->stream : nullptr);
@@ -1035,6 +1251,7 @@ rbf_status rbf_solve_device(rbf_problem* p, const rbf_solve_opts* opts, const do
                             double* d_lambda_out, rbf_solve_info* info) {
     if (!p || !d_lambda_out) return fail(RBF_EINVAL, "NULL argument");
     try {
+        MarkOnExit mk{p, as_stream(opts ? opts->stream : nullptr)};
         rbf_status s = solve_impl(p, opts, d_lambda0, true, nullptr, info);
         if (s != RBF_OK && s != RBF_ENOCONV && s != RBF_EBREAKDOWN) return s;
         hipStream_t st = as_stream(opts ? opts->stream : nullptr);
@@ -1062,8 +1279,8 @@ rbf_status rbf_evaluate(const rbf_problem* p, const double* targets, long long m
             hipError_t e = hipMemcpy(out, dout, sizeof(double) * m, hipMemcpyDeviceToHost);
             if (e != hipSuccess) s = fail(RBF_EDEVICE, "copy out: %s", hipGetErrorString(e));
         }
-        q->release(dt);
-        q->release(dout);
+        q->release(dt, nullptr);
+        q->release(dout, nullptr);
         return s;
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_evaluate");
@@ -1074,6 +1291,7 @@ rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, lo
                                double* d_out, void* stream) {
     if (!p) return fail(RBF_EINVAL, "NULL problem");
     try {
+        MarkOnExit mk{p, as_stream(stream)};
         return evaluate_impl(p, d_targets, m, d_out, as_stream(stream));
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_evaluate_device");
@@ -1081,6 +1299,17 @@ rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, lo
 }
 
 void rbf_destroy(rbf_problem* p) { delete p; }
+
+rbf_status rbf_block_cache(int device, int trim, size_t* idle_bytes) {
+    try {
+        BlockCache& c = BlockCache::get();
+        if (idle_bytes) *idle_bytes = c.idle_bytes(device);
+        if (trim) (void)c.trim(device);
+        return RBF_OK;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_block_cache");
+    }
+}
 
 rbf_status rbf_grid(const rbf_problem* p, double* out4, long long* ncxy) {
     if (!p || !out4 || !ncxy) return fail(RBF_EINVAL, "NULL argument");
@@ -1113,8 +1342,8 @@ rbf_status rbf_neighbor_counts(rbf_problem* p, int* nnb, long long* total) {
         HIP_TRY(rbf::launch_unpermute_int(d_sorted, p->perm, p->n, d_orig, nullptr));
         if (nnb) HIP_TRY(hipMemcpy(nnb, d_orig, sizeof(int) * p->n, hipMemcpyDeviceToHost));
         HIP_TRY(hipDeviceSynchronize());
-        p->release(d_sorted);
-        p->release(d_orig);
+        p->release(d_sorted, nullptr);
+        p->release(d_orig, nullptr);
         if (total) *total = p->interactions;
         return RBF_OK;
     } catch (...) {
@@ -1127,6 +1356,7 @@ rbf_status rbf_matvec_device(rbf_problem* p, const double* d_w, double* d_y,
     if (!p || !d_w || !d_y) return fail(RBF_EINVAL, "NULL argument");
     if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_EINVAL, "bad precision");
     hipStream_t st = as_stream(stream);
+    MarkOnExit mk{p, st};
     try {
         if (order == RBF_ORDER_SORTED) return matvec(p, precision, d_w, d_y, st);
         if (order != RBF_ORDER_ORIGINAL) return fail(RBF_EINVAL, "bad order");
@@ -1137,8 +1367,8 @@ rbf_status rbf_matvec_device(rbf_problem* p, const double* d_w, double* d_y,
         RBF_TRY(matvec(p, precision, ws, ys, st));
         HIP_TRY(rbf::launch_unpermute(ys, p->perm, p->n, d_y, st));
         HIP_TRY(hipStreamSynchronize(st));
-        p->release(ws);
-        p->release(ys);
+        p->release(ws, st);
+        p->release(ys, st);
         return RBF_OK;
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_matvec_device");
@@ -1150,6 +1380,7 @@ rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d
     if (!p || !d_v || !d_z) return fail(RBF_EINVAL, "NULL argument");
     if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_EINVAL, "bad precision");
     hipStream_t st = as_stream(stream);
+    MarkOnExit mk{p, st};
     try {
         if (order == RBF_ORDER_SORTED) return rasm(p, precision, d_v, d_z, st);
         if (order != RBF_ORDER_ORIGINAL) return fail(RBF_EINVAL, "bad order");
@@ -1163,8 +1394,8 @@ rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) s = fail(RBF_EDEVICE, "%s", hipGetErrorString(e));
         }
-        p->release(vs);
-        p->release(zs);
+        p->release(vs, st);
+        p->release(zs, st);
         return s;
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_precond_apply_device");

@@ -168,6 +168,13 @@ hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const doub
 hipError_t launch_rasm_apply32(const PrecondArgs& a, const float* Z, const double* v,
                                double* z, hipStream_t st);
 
+// ---- device block cache (capi.cpp) -------------------------------------------
+// Allocation from, and return to, the library's cache of device blocks (see
+// rbf_block_cache); *got is the size actually held.  cached_free takes a
+// block back once the work enqueued on st before the call has finished.
+hipError_t cached_alloc(int dev, size_t bytes, void** out, size_t* got);
+void cached_free(int dev, void* p, size_t bytes, hipStream_t st);
+
 // ---- Krylov vector operations (krylov.hip) -----------------------------------
 constexpr int kDotBlocks = 1024;
 // out[k] = <V_k, w> for k < nv (V column k at V + k*ldv), deterministic

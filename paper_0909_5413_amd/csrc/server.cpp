@@ -4,8 +4,10 @@
 // on submission and admitted in arrival order whenever fewer than max_active
 // are on the device and their predicted device footprint fits the remaining
 // budget (a request larger than the whole budget is admitted alone).  Each
-// admitted request runs on a worker thread with its own HIP stream (default
-// priority): setup, preconditioner, solve, copy-out, release.  Requests that
+// admitted request runs on a worker thread, on that worker's own HIP stream
+// (default priority, created once per worker): setup, preconditioner, solve,
+// copy-out, release.  Device buffers come from the library's block cache, so
+// a request neither maps fresh memory nor waits for the device on release.  Requests that
 // arrive while others run are admitted as slots and memory free up, and their
 // kernels overlap on the device with the running ones.  Every request runs
 // exactly the same launches as a lone rbf_solve_device call, so its weights
@@ -25,6 +27,7 @@
 #include <vector>
 
 #include "../../include/rbf.h"
+#include "rbf_internal.hpp"
 
 namespace {
 
@@ -112,23 +115,26 @@ struct rbf_server {
         }
     }
 
-    void run(Request* r) {
+    void run(Request* r, hipStream_t st) {
         (void)hipSetDevice(device);
-        hipStream_t st = nullptr;
         rbf_problem* h = nullptr;
-        double *d_pts = nullptr, *d_vals = nullptr, *d_lam = nullptr;
-        rbf_status s = RBF_OK;
+        void *b_pts = nullptr, *b_vals = nullptr, *b_lam = nullptr;
+        size_t g_pts = 0, g_vals = 0, g_lam = 0;
+        rbf_status s = st ? RBF_OK : RBF_EDEVICE;
         auto hip = [&](hipError_t e) {
             if (e != hipSuccess && s == RBF_OK) s = e == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE;
             return s == RBF_OK;
         };
         const size_t nb = sizeof(double) * (size_t)r->n;
-        if (hip(hipStreamCreate(&st)) && hip(hipMalloc(&d_pts, 2 * nb)) &&
-            hip(hipMalloc(&d_vals, nb)) && hip(hipMalloc(&d_lam, nb)) &&
-            hip(hipMemcpyAsync(d_pts, r->pts.data(), 2 * nb, hipMemcpyHostToDevice, st)) &&
-            hip(hipMemcpyAsync(d_vals, r->vals.data(), nb, hipMemcpyHostToDevice, st))) {
-            s = rbf_setup_device(d_pts, d_vals, r->n, r->sigma, r->cutoff, r->overlap, st, &h);
+        if (s == RBF_OK && hip(rbf::cached_alloc(device, 2 * nb, &b_pts, &g_pts)) &&
+            hip(rbf::cached_alloc(device, nb, &b_vals, &g_vals)) &&
+            hip(rbf::cached_alloc(device, nb, &b_lam, &g_lam)) &&
+            hip(hipMemcpyAsync(b_pts, r->pts.data(), 2 * nb, hipMemcpyHostToDevice, st)) &&
+            hip(hipMemcpyAsync(b_vals, r->vals.data(), nb, hipMemcpyHostToDevice, st))) {
+            s = rbf_setup_device(static_cast<double*>(b_pts), static_cast<double*>(b_vals), r->n,
+                                 r->sigma, r->cutoff, r->overlap, st, &h);
         }
+        double* d_lam = static_cast<double*>(b_lam);
         if (s == RBF_OK) s = rbf_precond_setup(h, r->opts.precision, st);
         rbf_solve_info info{};
         if (s == RBF_OK) {
@@ -146,10 +152,9 @@ struct rbf_server {
         info.history = nullptr;
         info.history_len = 0;
         rbf_destroy(h);
-        if (d_pts) (void)hipFree(d_pts);
-        if (d_vals) (void)hipFree(d_vals);
-        if (d_lam) (void)hipFree(d_lam);
-        if (st) (void)hipStreamDestroy(st);
+        if (b_pts) rbf::cached_free(device, b_pts, g_pts, st);
+        if (b_vals) rbf::cached_free(device, b_vals, g_vals, st);
+        if (b_lam) rbf::cached_free(device, b_lam, g_lam, st);
         std::lock_guard<std::mutex> lk(mu);
         r->status = s;
         r->info = info;
@@ -167,16 +172,21 @@ struct rbf_server {
     }
 
     void worker_loop() {
+        (void)hipSetDevice(device);
+        hipStream_t st = nullptr;
+        if (hipStreamCreate(&st) != hipSuccess) st = nullptr;
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
             cv_sched.wait(lk, [&] { return !ready.empty() || (stopping && queue.empty() && ready.empty()); });
-            if (ready.empty()) return;
+            if (ready.empty()) break;
             Request* r = ready.front();
             ready.pop_front();
             lk.unlock();
-            run(r);
+            run(r, st);
             lk.lock();
         }
+        lk.unlock();
+        if (st) (void)hipStreamDestroy(st);
     }
 };
 

@@ -118,3 +118,26 @@ def test_admission_budget_and_failures(torch_dev):
         assert R.rbf_server_stats(srv)["bytes_charged"] == 0
     finally:
         R.rbf_server_destroy(srv)
+
+
+def test_block_cache_reuse_is_clean(torch_dev):
+    """Blocks handed back by one problem and reused by the next (dirty, of a
+    nearby size) leave every result unchanged, and trimming empties the cache."""
+    reqs = mix(3, 999000)
+    R.rbf_block_cache(-1, trim=True)
+    assert R.rbf_block_cache(-1) == 0
+    w, pts, f, prec = reqs[0]
+    say("cache fresh", w.name, w.n)
+    lam0, st0 = alone(w, pts, f, R.RBF_FP64)
+    idle = R.rbf_block_cache(-1)
+    say("cache idle bytes", idle)
+    assert idle > 0
+    for w1, p1, f1, _ in reqs[1:]:
+        say("cache other", w1.name, w1.n)
+        alone(w1, p1, f1, R.RBF_MIXED)
+    say("cache reuse", w.name, w.n)
+    lam1, st1 = alone(w, pts, f, R.RBF_FP64)
+    assert st1 == st0
+    assert np.array_equal(lam1, lam0)
+    R.rbf_block_cache(-1, trim=True)
+    assert R.rbf_block_cache(-1) == 0
