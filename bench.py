@@ -189,8 +189,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=128,
-                    help="requests of the serving stream to run (the configuration has 512)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests of the serving stream to run (the configuration's 512)")
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-max-iters", type=int, default=300)
     args = ap.parse_args()

@@ -144,8 +144,10 @@ rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, lo
                                double* d_out, void* stream);
 
 /* Release everything the handle owns (NULL is ignored).  Waits for the work
- * that the handle's calls enqueued, on whatever stream, and no other work; the
- * handle's device buffers go to the library's block cache (below). */
+ * that the handle's calls enqueued and no other work, through an event
+ * recorded on the stream of the handle's last call, which must therefore
+ * still exist; the handle's device buffers go to the library's block cache
+ * (below). */
 void rbf_destroy(rbf_problem* p);
 
 /* Device block cache.  Buffers a handle gives back (on rbf_destroy, or
@@ -244,6 +246,7 @@ typedef struct {
     double t_run;              /* seconds from admission to completion */
     double latency;            /* t_queue + t_run */
     size_t predicted_bytes;    /* footprint charged against the budget */
+    char message[256];         /* rbf_last_error of the failing call, or "" */
 } rbf_request_result;
 
 void rbf_server_default_opts(rbf_server_opts* opts);

@@ -79,7 +79,7 @@ class ServerOpts(C.Structure):
 class RequestResult(C.Structure):
     _fields_ = [("status", C.c_int), ("info", SolveInfo), ("t_queue", C.c_double),
                 ("t_run", C.c_double), ("latency", C.c_double),
-                ("predicted_bytes", C.c_size_t)]
+                ("predicted_bytes", C.c_size_t), ("message", C.c_char * 256)]
 
 
 def lib():
@@ -328,7 +328,7 @@ def rbf_server_wait(srv: int, rid: int, n: int, ok=(RBF_OK, RBF_ENOCONV)):
     res = RequestResult()
     st = lib().rbf_server_wait(srv, rid, _ptr(lam), C.byref(res))
     if st not in ok:
-        raise RbfError(st, "rbf_server_wait", last_error())
+        raise RbfError(st, "rbf_server_wait", res.message.decode() or last_error())
     return (lam if st in (RBF_OK, RBF_ENOCONV) else None), res, st
 
 

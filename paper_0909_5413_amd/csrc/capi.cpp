@@ -72,12 +72,12 @@ struct DevBuf {
 // Device blocks released by problems, kept for reuse by later allocations of
 // about the same size.  A fresh multi-GB hipMalloc maps new pages and hipFree
 // waits for the whole device, which together cost more than a solve when
-// problems of varying sizes follow one another (the serving loop).  A block
-// released while work may still use it carries an event recorded on that
-// work's stream; the next owner waits for the event before the block is
-// handed out.  Idle blocks are returned to the runtime when an allocation
-// fails, when they exceed a quarter of the device memory, or on
-// rbf_trim_cache.
+// problems of varying sizes follow one another (the serving loop).  A block is
+// taken back only once the work that used it has finished: the releasing call
+// waits for its own stream first (at that point nearly always idle already),
+// so that nothing in the cache refers to a stream that may be destroyed later.
+// Idle blocks are returned to the runtime when an allocation fails, when they
+// exceed a quarter of the device memory, or on rbf_block_cache.
 class BlockCache {
 public:
     static BlockCache& get() {
@@ -114,11 +114,6 @@ public:
                 }
         }
         if (found) {
-            hipError_t e = settle(b);
-            if (e != hipSuccess) {
-                (void)hipFree(b.p);
-                return e;
-            }
             *out = b.p;
             *got = b.bytes;
             return hipSuccess;
@@ -139,19 +134,14 @@ public:
         *got = r;
         return hipSuccess;
     }
-    // Takes back a block; work enqueued on `st` before this call may still use it.
+    // Takes back a block; pending: work enqueued on `st` before this call may
+    // still use it (waited for here).
     void put(int dev, void* p, size_t bytes, hipStream_t st, bool pending) {
-        Blk b{p, bytes, dev, nullptr};
-        if (pending) {
-            if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
-                b.ev = nullptr;
-                (void)hipStreamSynchronize(st);
-            } else if (hipEventRecord(b.ev, st) != hipSuccess) {
-                (void)hipEventDestroy(b.ev);
-                b.ev = nullptr;
-                (void)hipStreamSynchronize(st);
-            }
+        if (pending && hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipDeviceSynchronize();
         }
+        Blk b{p, bytes, dev};
         std::vector<Blk> evict;
         {
             std::lock_guard<std::mutex> lk(mu_);
@@ -167,10 +157,7 @@ public:
                 it = idle_.erase(it);
             }
         }
-        for (Blk& e : evict) {
-            (void)settle(e);
-            (void)hipFree(e.p);
-        }
+        for (Blk& e : evict) (void)hipFree(e.p);
     }
     // Returns the idle blocks of device dev (all devices if dev < 0) to the
     // runtime; the number of bytes freed.
@@ -190,7 +177,6 @@ public:
         }
         size_t freed = 0;
         for (Blk& e : evict) {
-            (void)settle(e);
             (void)hipFree(e.p);
             freed += e.bytes;
         }
@@ -209,17 +195,7 @@ private:
         void* p;
         size_t bytes;
         int dev;
-        hipEvent_t ev;     // completion of the last work that used the block, or NULL
     };
-    static hipError_t settle(Blk& b) {
-        hipError_t e = hipSuccess;
-        if (b.ev) {
-            e = hipEventSynchronize(b.ev);
-            (void)hipEventDestroy(b.ev);
-            b.ev = nullptr;
-        }
-        return e;
-    }
     size_t cap_locked(int dev) {
         auto it = cap_.find(dev);
         if (it != cap_.end()) return it->second;

@@ -18,6 +18,8 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
+#include <string>
 #include <deque>
 #include <map>
 #include <memory>
@@ -45,6 +47,7 @@ struct Request {
     std::vector<double> lambda;
     rbf_status status = RBF_OK;
     rbf_solve_info info{};
+    std::string message;
     bool done = false;
 };
 
@@ -121,8 +124,12 @@ struct rbf_server {
         void *b_pts = nullptr, *b_vals = nullptr, *b_lam = nullptr;
         size_t g_pts = 0, g_vals = 0, g_lam = 0;
         rbf_status s = st ? RBF_OK : RBF_EDEVICE;
+        std::string msg;
         auto hip = [&](hipError_t e) {
-            if (e != hipSuccess && s == RBF_OK) s = e == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE;
+            if (e != hipSuccess && s == RBF_OK) {
+                s = e == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE;
+                msg = std::string("request staging: ") + hipGetErrorString(e);
+            }
             return s == RBF_OK;
         };
         const size_t nb = sizeof(double) * (size_t)r->n;
@@ -133,14 +140,19 @@ struct rbf_server {
             hip(hipMemcpyAsync(b_vals, r->vals.data(), nb, hipMemcpyHostToDevice, st))) {
             s = rbf_setup_device(static_cast<double*>(b_pts), static_cast<double*>(b_vals), r->n,
                                  r->sigma, r->cutoff, r->overlap, st, &h);
+            if (s != RBF_OK) msg = std::string("setup: ") + rbf_last_error();
         }
         double* d_lam = static_cast<double*>(b_lam);
-        if (s == RBF_OK) s = rbf_precond_setup(h, r->opts.precision, st);
+        if (s == RBF_OK) {
+            s = rbf_precond_setup(h, r->opts.precision, st);
+            if (s != RBF_OK) msg = std::string("preconditioner: ") + rbf_last_error();
+        }
         rbf_solve_info info{};
         if (s == RBF_OK) {
             rbf_solve_opts o = r->opts;
             o.stream = st;
             s = rbf_solve_device(h, &o, nullptr, d_lam, &info);
+            if (s != RBF_OK) msg = std::string("solve: ") + rbf_last_error();
         }
         if (s == RBF_OK || s == RBF_ENOCONV) {
             r->lambda.resize(r->n);
@@ -157,6 +169,7 @@ struct rbf_server {
         if (b_lam) rbf::cached_free(device, b_lam, g_lam, st);
         std::lock_guard<std::mutex> lk(mu);
         r->status = s;
+        r->message = s == RBF_OK ? std::string() : msg;
         r->info = info;
         r->t_done = clk::now();
         r->done = true;
@@ -270,6 +283,7 @@ rbf_status rbf_server_wait(rbf_server* s, long long id, double* lambda_out,
         result->t_run = sec(r->t_done - r->t_admit).count();
         result->latency = sec(r->t_done - r->t_submit).count();
         result->predicted_bytes = r->predicted;
+        std::snprintf(result->message, sizeof result->message, "%s", r->message.c_str());
     }
     const rbf_status st = r->status;
     s->reqs.erase(it);
