@@ -51,15 +51,15 @@ def block_sizes(cell_start, ncx, ncy, overlap=1):
 
 def step_kernel_flops(n_omega):
     """Algorithmic FP64 flops of the factorisation-step launches for blocks of
-    n points: per 32-column block column J, the update of the rows below the
-    diagonal block (2 * 32 * J flops per row) and their solve against the
-    32x32 diagonal factor (32^2 flops per row)."""
+    n points: per 64-column block column J, the update of the rows below the
+    diagonal block (2 * 64 * J flops per row) and their solve against the
+    64x64 diagonal factor (64^2 flops per row)."""
     import numpy as np
     total = 0.0
     for n in np.asarray(n_omega, dtype=np.int64):
-        J = np.arange(0, max(int(n) - 32, 0), 32, dtype=np.float64)
-        rows = n - J - 32
-        total += float(np.sum(rows * (64.0 * J + 1024.0)))
+        J = np.arange(0, max(int(n) - 64, 0), 64, dtype=np.float64)
+        rows = n - J - 64
+        total += float(np.sum(rows * (128.0 * J + 4096.0)))
     return total
 
 

@@ -201,11 +201,11 @@ rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precisio
 
 /* Kernels of the local factorisations (rbf_precond_setup), by kind. */
 typedef enum {
-    RBF_K_ASSEMBLE = 0,   /* local matrices and their first diagonal block */
-    RBF_K_CHOL_STEP = 1,  /* block-column update and panel solve, one launch per block column */
-    RBF_K_CHOL_DIAG = 2,  /* next diagonal block: product and 32x32 Cholesky */
+    RBF_K_ASSEMBLE = 0,   /* local matrices and their first 64x64 diagonal factor */
+    RBF_K_CHOL_STEP = 1,  /* 64-column block-column update and panel solve, one launch each */
+    RBF_K_CHOL_DIAG = 2,  /* next diagonal block: product and 64x64 Cholesky */
     RBF_K_FORWARD = 3,    /* forward solve L W = E_C on the trailing rows */
-    RBF_K_BACK = 4,       /* back solve L^T X = W, one launch per block row */
+    RBF_K_BACK = 4,       /* back solve L^T X = W, one launch per 32-row block row */
     RBF_K_SETUP_KINDS = 5
 } rbf_setup_kernel;
 

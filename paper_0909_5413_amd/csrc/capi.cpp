@@ -544,7 +544,7 @@ rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals,
         if (own > 0) maxo = std::max(maxo, p->n_omega[c]);
         p->nc_max = std::max(p->nc_max, own);
     }
-    p->np_max = (maxo + 31) / 32 * 32;
+    p->np_max = (maxo + 63) / 64 * 64;   // the factorisation advances 64 columns at a time
 
     // table e^{-n/128} covering the matvec's exponents down to -cutoff^2/(2 sigma^2)
     const double xmin = p->cutoff * p->cutoff / (2.0 * p->sigma * p->sigma);
@@ -653,7 +653,7 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     if (s == RBF_OK) s = p->alloc_n(&status, nc);
     if (s == RBF_OK) s = p->alloc_n(&meta, pad);
     if (s == RBF_OK) s = p->alloc_n(&lvl, pad);
-    if (s == RBF_OK) s = p->alloc_n(&lt, 2 * pad * 1024);
+    if (s == RBF_OK) s = p->alloc_n(&lt, 2 * pad * 2048);
     auto release_all = [&]() {
         if (scratch) p->release(scratch, st);
         if (status) p->release(status, st);

@@ -9,10 +9,10 @@
 //
 // Setup, for every cell:
 //  1. members: neighbour cells in (dy, dx) order, each a contiguous sorted
-//     range, the cell's own points last; padded to n_p = 32 * ceil(n/32) by
+//     range, the cell's own points last; padded to n_p = 64 * ceil(n/64) by
 //     leading identity rows so every block boundary is aligned;
 //  2. A_c[p][q] = phi(|x_p - x_q|), the untruncated normalised Gaussian;
-//  3. A_c = L L^T by a left-looking blocked Cholesky (32-column block columns);
+//  3. A_c = L L^T by a left-looking blocked Cholesky (64-column block columns);
 //  4. X = A_c^{-1} E_C (E_C = the centre columns of the identity) by a blocked
 //     forward solve L W = E_C on the trailing rows only, then a blocked back
 //     solve L^T X = W; X's columns, without the padding rows, are Z_c's rows
@@ -88,15 +88,17 @@ __device__ __forceinline__ int member_index(const int* rb, const int* re, int nr
 
 // ===========================================================================
 // Setup on the matrix cores, batched in lockstep.  Each cell of a batch (a
-// slot) keeps its n_p x n_p lower triangle in a scratch slot, stored by block
-// rows (see roff).  The left-looking blocked Cholesky advances one 32-column
-// block column J at a time for every slot together, one launch per J: each
-// workgroup takes a 256-row tile below the diagonal block, updates it with the
-// finished block columns as MFMA tiles (the result lands in LDS), solves
-// x L_JJ^T = a for its rows by substitution (one row per thread, L_JJ
-// broadcast from LDS), and writes the rows back.  A second launch then forms
-// and factors the next diagonal block of every slot, one small single-wave
-// workgroup each.  The centre rows of the inverse follow: one
+// slot) keeps its n_p x n_p lower triangle in a scratch slot, stored by
+// 32-row block rows (see roff).  The left-looking blocked Cholesky advances one
+// 64-column block column J at a time for every slot together, one launch per
+// J: each workgroup takes a 128-row tile below the diagonal block, updates it
+// with the finished block columns as MFMA tiles (accumulators in registers),
+// solves x L_JJ^T = a for its rows in two 32-column halves (substitution, one
+// row per thread, the diagonal blocks broadcast from LDS; the coupling block on
+// MFMA), and writes the rows back.  A second launch then forms and factors the
+// next 64x64 diagonal block of every slot, one small single-wave workgroup
+// each.  64 columns per step halve the re-reads of the finished columns that
+// a left-looking update makes, against 32.  The centre rows of the inverse follow: one
 // launch for the forward solve on the trailing rows, one launch per block row
 // of the back solve.  Every launch carries thousands of independent
 // workgroups, so one cell's serial steps overlap with other cells' work.
@@ -162,13 +164,15 @@ __device__ __forceinline__ float rsqrt_t(float x) {
 
 constexpr int kT2 = 256;        // threads of the assembly and forward-solve kernels (4 waves)
 constexpr int kW2 = kT2 / 64;
+constexpr int kFB = 2 * kNB;    // columns of a factorisation block column; n_p is a multiple
 constexpr int kTS = 256;        // threads of a factorisation step (4 waves)
 constexpr int kWS = kTS / 64;
-constexpr int kRows2 = 256;     // rows per step tile
-constexpr int kRT2 = kRows2 / 16 / kWS;   // row tiles per wave (4)
-static_assert(kRows2 == kTS, "the substitution gives one row to each thread");
-constexpr int kXS = kRows2 + 1; // padded LDS row of a staged tile (conflict-free MFMA stores)
+constexpr int kRows = 128;      // rows per step tile
+static_assert(kRows <= kTS, "the substitution gives one row to each thread");
+static_assert(kRows == 2 * 16 * kWS, "two row tiles per wave in a full tile");
+constexpr int kXS = kRows + 1;  // padded LDS row of a staged tile (conflict-free MFMA stores)
 constexpr int kTri = kNB * (kNB + 1) / 2;
+constexpr int kLtElems = 2 * kNB * kNB;   // per slot: both diagonal 32x32 blocks of L_JJ
 
 // Index of (k, j), j >= k, in the packed upper triangle of a 32x32 block.
 __host__ __device__ constexpr int tri(int k, int j) { return kNB * k - k * (k - 1) / 2 + (j - k); }
@@ -183,46 +187,43 @@ __device__ __forceinline__ size_t roff(int row) {
     return (size_t)(32 * (I + 1)) * (size_t)(16 * I + (row & 31));
 }
 
-template <typename T>
-struct StepLds {
-    T X[kNB][kXS];                    // the tile's rows, one column per thread
-    T Lt[kTri];                       // L_JJ transposed (packed), reciprocal pivots on the diagonal
-};
 
-// X[c][r] = A[R + r][J + c] - sum_{k < J} L[R + r][k] L[J + c][k] for the
-// nrow (a multiple of 32, <= 256) rows of the tile, J > 0.  MFMA tiles with
-// no LDS staging and no barriers: the contraction index of an MFMA may be
-// permuted as long as A and B use the same permutation, so over a chunk of 16
-// k values lane group g = l/16 owns k = K+4g .. K+4g+3 and loads them from its
-// row with one vector load; step s of the chunk uses element s.  Each wave
-// loads its own M row tiles (three register buffers: two chunks in flight
-// while one is multiplied) and both column tiles (shared by the waves through
-// the caches; two buffers).  Six chunks per loop pass keep every buffer index
-// a constant and the body free of branches, so each multiply waits only for
-// its own loads.
+// The update of a step tile: acc[t][cb] += sum_{k0 <= k < J} L[row][k] L[J + 16 cb + col][k]
+// for the wave's row tiles t (rows R + 16 (wave + 4 t) ..) and the four 16-column
+// tiles of the block column.  MFMA tiles with no LDS staging and no barriers:
+// the contraction index of an MFMA may be permuted as long as A and B use the
+// same permutation, so over a chunk of 16 k values lane group g = l/16 owns
+// k = K+4g .. K+4g+3 and loads them from its row with one vector load; step s
+// of the chunk uses element s.  Each wave loads its own M row tiles (three
+// register buffers: two chunks in flight while one is multiplied) and the four
+// column tiles (shared by the waves through the caches; two buffers).  Six
+// chunks per loop pass keep every buffer index a constant and the body free of
+// branches, so each multiply waits only for its own loads.  Columns below k0
+// are zero in every row involved (leading identity padding) and are skipped.
 template <typename T, int M>
 struct UpdateRegs {
     v4<T> a[3][M];
-    v4<T> b[2][2];
-    v4<T> acc[M][2];
+    v4<T> b[2][4];
+    v4<T> acc[M][4];
     const T* arow[M];
-    const T* brow[2];
+    const T* brow[4];
 
     __device__ __forceinline__ void load_a(int buf, int ch) {
 #pragma unroll
         for (int t = 0; t < M; ++t) a[buf][t] = load4(arow[t] + 16 * ch);
     }
     __device__ __forceinline__ void load_b(int buf, int ch) {
-        b[buf][0] = load4(brow[0] + 16 * ch);
-        b[buf][1] = load4(brow[1] + 16 * ch);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) b[buf][cb] = load4(brow[cb] + 16 * ch);
     }
     __device__ __forceinline__ void mma(int ba, int bb) {
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
 #pragma unroll
             for (int t = 0; t < M; ++t) {
-                acc[t][0] = mfma(a[ba][t][st], b[bb][0][st], acc[t][0]);
-                acc[t][1] = mfma(a[ba][t][st], b[bb][1][st], acc[t][1]);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[t][cb] = mfma(a[ba][t][st], b[bb][cb][st], acc[t][cb]);
             }
         }
     }
@@ -239,62 +240,31 @@ struct UpdateRegs {
             }
         }
     }
+    // acc[t][cb] += the products (the caller initialises acc)
+    __device__ __forceinline__ void update(const T* __restrict__ A, int J, int k0, int R,
+                                           int wave) {
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, g = lane >> 4;
+        if (J == 0) return;
+#pragma unroll
+        for (int t = 0; t < M; ++t) arow[t] = A + roff(R + 16 * (wave + kWS * t) + i16) + k0 + 4 * g;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) brow[cb] = A + roff(J + 16 * cb + i16) + k0 + 4 * g;
+        const int nchunk = (J - k0) / 16;   // >= 2, even
+        load_a(0, 0);
+        load_a(1, 1);
+        load_b(0, 0);
+        int c = 0;
+        for (; c + 8 <= nchunk; c += 6) run<99>(c);
+        const int rest = nchunk - c;   // 2, 4 or 6
+        if (rest == 2)
+            run<2>(c);
+        else if (rest == 4)
+            run<4>(c);
+        else
+            run<6>(c);
+    }
 };
-
-template <typename T, int M>
-__device__ __forceinline__ void update_core(const T* __restrict__ A, int J, int R, int wave,
-                                            T (*X)[kXS]) {
-    const int lane = threadIdx.x & 63;
-    const int i16 = lane & 15, g = lane >> 4;
-    UpdateRegs<T, M> u;
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-        u.acc[t][0] = u.acc[t][1] = v4<T>{0, 0, 0, 0};
-        u.arow[t] = A + roff(R + 16 * (wave + kWS * t) + i16) + 4 * g;
-    }
-    u.brow[0] = A + roff(J + i16) + 4 * g;
-    u.brow[1] = A + roff(J + 16 + i16) + 4 * g;
-    const int nchunk = J / 16;   // >= 2, even
-    u.load_a(0, 0);
-    u.load_a(1, 1);
-    u.load_b(0, 0);
-    int c = 0;
-    for (; c + 8 <= nchunk; c += 6) u.template run<99>(c);
-    const int rest = nchunk - c;   // 2, 4 or 6
-    if (rest == 2)
-        u.template run<2>(c);
-    else if (rest == 4)
-        u.template run<4>(c);
-    else
-        u.template run<6>(c);
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-        const int tile = wave + kWS * t;
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rl = 16 * tile + out_row<T>(g, v);
-                const int col = 16 * cb + i16;
-                X[col][rl] = A[roff(R + rl) + J + col] - u.acc[t][cb][v];
-            }
-    }
-}
-
-template <typename T>
-__device__ void update_tile(const T* __restrict__ A, int J, int R, int nrow, T (*X)[kXS]) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ntile = nrow / 16;
-    const int mine = (ntile - wave + kWS - 1) / kWS;   // row tiles of this wave (uniform)
-    static_assert(kRT2 == 4, "row tiles per wave");
-    switch (mine) {
-        case 4: update_core<T, 4>(A, J, R, wave, X); break;
-        case 3: update_core<T, 3>(A, J, R, wave, X); break;
-        case 2: update_core<T, 2>(A, J, R, wave, X); break;
-        case 1: update_core<T, 1>(A, J, R, wave, X); break;
-        default: break;
-    }
-}
 
 // X[c][r] = A[R + r][J + c] (coalesced pair loads), r < nrow.
 template <typename T>
@@ -319,10 +289,11 @@ __device__ void store_tile(T* __restrict__ A, int J, int R, int nrow, T (*X)[kXS
     }
 }
 
-// Row tid of the tile: x L_JJ^T = a in place (column tid of X), column by
-// column so that every step is 31 - k independent FMAs.  Lt holds L_JJ
-// transposed (Lt[k][j] = L[j][k], j > k) with the reciprocal pivots on its
-// diagonal; every lane reads the same Lt entries (LDS broadcasts).
+// Row tid of the tile: x L_DD^T = a in place (column tid of X) for a 32x32
+// diagonal block D of L_JJ, column by column so that every step is 31 - k
+// independent FMAs.  Lt holds L_DD transposed (Lt[k][j] = L[j][k], j > k)
+// with the reciprocal pivots on its diagonal; every lane reads the same Lt
+// entries (LDS broadcasts).
 template <typename T>
 __device__ __forceinline__ void trsm_tile(const T* Lt, int nrow, T (*X)[kXS]) {
     const int tid = threadIdx.x;
@@ -340,30 +311,36 @@ __device__ __forceinline__ void trsm_tile(const T* Lt, int nrow, T (*X)[kXS]) {
     for (int q = 0; q < kNB; ++q) X[q][tid] = x[q];
 }
 
-// Factor the 32x32 diagonal block J0 (lower part of D) in wave 0's registers
-// (lane i holds row i; broadcasts by readlane, no barriers).  Step k: the
-// pivot, its reciprocal square root, column k of L written to A and,
+// Factor the 64x32 panel at J0 (rows J0 .. J0 + 63, columns J0 .. J0 + 31):
+// its top 32x32 block Dt (lower part) is the diagonal block, its bottom block
+// Db (NULL: a 32x32 block alone) the rows below.  Wave 0's registers, lane i
+// holding panel row i; broadcasts by readlane, no barriers.  Step k: the pivot,
+// its reciprocal square root, column k of L written to A, to Dt / Db (below
+// the diagonal; the reciprocal pivot on it) and, for the diagonal block,
 // transposed with the reciprocal pivot on the diagonal, to Lt (full 32x32
 // layout, column k at Lt[k * 32 ..]), then the rank-1 update of the rows
-// below.  Returns 0 or J0 + the failing 1-based pivot index (all threads).
+// below, bottom rows included.  Returns 0 or J0 + the failing 1-based pivot
+// index (all threads).
 template <typename T>
-__device__ __forceinline__ int factor_diag_block(T* __restrict__ A, int J0, T (*D)[kNB + 1],
-                                                 int* flag, T* __restrict__ Lt) {
+__device__ __forceinline__ int factor_panel(T* __restrict__ A, int J0, T (*Dt)[kNB + 1],
+                                            T (*Db)[kNB + 1], int* flag, T* __restrict__ Lt) {
     const int tid = threadIdx.x;
     if (tid < 64) {
+        const bool top = tid < kNB;
+        const bool own = top || Db != nullptr;
         const int i = tid & 31;
-        const bool own = tid < kNB;
-        T* arow = A + roff(J0 + i) + J0;
+        T* arow = A + roff(J0 + (top ? i : kNB + i)) + J0;
         T r[kNB];
 #pragma unroll
-        for (int c = 0; c < kNB; ++c) r[c] = (c <= i) ? D[i][c] : T(0);
+        for (int c = 0; c < kNB; ++c)
+            r[c] = top ? ((c <= i) ? Dt[i][c] : T(0)) : (Db ? Db[i][c] : T(0));
         int bad = 0;
 #pragma unroll
         for (int k = 0; k < kNB; ++k) {
             const T piv = readlane_t(r[k], k);
             if (!bad && !(piv > T(0))) bad = k + 1;   // uniform; later values are moot
             const T y = rsqrt_t(piv);
-            const T l = (i == k) ? piv * y : r[k] * y;
+            const T l = (top && i == k) ? piv * y : r[k] * y;
             r[k] = l;
 #pragma unroll
             for (int j = k + 1; j < kNB; ++j) {
@@ -372,15 +349,79 @@ __device__ __forceinline__ int factor_diag_block(T* __restrict__ A, int J0, T (*
                 // broadcast values stay short-lived (no SGPR spills)
                 __asm__ volatile("" : "+v"(r[j]));
             }
-            if (own && i >= k) {
+            if (own && (!top || i >= k)) {
                 arow[k] = l;
-                Lt[k * kNB + i] = (i == k) ? y : l;
+                if (top) {
+                    const T lk = (i == k) ? y : l;
+                    Lt[k * kNB + i] = lk;
+                    Dt[i][k] = lk;
+                } else {
+                    Db[i][k] = l;
+                }
             }
         }
         if (tid == 0) *flag = bad ? J0 + bad : 0;
     }
     __syncthreads();
     return *flag;
+}
+
+// The 64x64 diagonal block L_JJ at J0 from D = A_JJ - (finished columns),
+// held as its three lower 32x32 blocks: the panel [D11; D21] factored in one
+// pass (L11, L21), D22 -= L21 L21^T on MFMA, D22 factored.  L_JJ goes to A;
+// lt receives the two diagonal blocks transposed with reciprocal pivots
+// (lt[0 .. 1023] and lt[1024 .. 2047], full layout).  Any block size >= 64
+// threads; wave 0 works.  Returns 0 or J0 + the failing 1-based pivot index
+// (all threads).
+template <typename T>
+struct Diag64 {
+    T D11[kNB][kNB + 1], D21[kNB][kNB + 1], D22[kNB][kNB + 1];
+    int flag;
+};
+
+template <typename T>
+struct StepLds {
+    T X[kNB][kXS];            // 32 columns of the tile's rows, one column per thread
+    T Lt1[kTri], Lt2[kTri];   // diagonal 32x32 blocks of L_JJ transposed (packed), reciprocal pivots
+    T L21[kNB][kNB + 1];      // L21[j][k] = L[J + 32 + j][J + k]
+};
+
+template <typename T>
+__device__ __forceinline__ void diag64_put(Diag64<T>& d, int r, int c, T v) {
+    if (r < kNB)
+        d.D11[r][c] = v;
+    else if (c < kNB)
+        d.D21[r - kNB][c] = v;
+    else
+        d.D22[r - kNB][c - kNB] = v;
+}
+
+template <typename T>
+__device__ int factor_diag64(T* __restrict__ A, int J0, Diag64<T>& d, T* __restrict__ lt) {
+    const int tid = threadIdx.x;
+    const int f1 = factor_panel<T>(A, J0, d.D11, d.D21, &d.flag, lt);
+    if (tid < 64) {
+        const int i16 = tid & 15, g = tid >> 4;
+        v4<T> t00 = {0, 0, 0, 0}, t10 = t00, t11 = t00;
+#pragma unroll
+        for (int s8 = 0; s8 < kNB / 4; ++s8) {
+            const int k = 4 * s8 + g;
+            const T a0 = d.D21[i16][k], a1 = d.D21[16 + i16][k];
+            t00 = mfma(a0, a0, t00);
+            t10 = mfma(a1, a0, t10);
+            t11 = mfma(a1, a1, t11);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = out_row<T>(g, v);
+            d.D22[r][i16] -= t00[v];
+            d.D22[16 + r][i16] -= t10[v];
+            d.D22[16 + r][16 + i16] -= t11[v];
+        }
+    }
+    __syncthreads();
+    const int f2 = factor_panel<T>(A, J0 + kNB, d.D22, nullptr, &d.flag, lt + kNB * kNB);
+    return f1 ? f1 : f2;
 }
 
 template <typename T>
@@ -485,14 +526,14 @@ template <typename T>
 struct AssembleLds {
     double mx[RBF_MAX_BLOCK];
     double my[RBF_MAX_BLOCK];
-    T D[kNB][kNB + 1];
+    Diag64<T> d;
     int rb[kMaxRanges], re[kMaxRanges];
-    int nranges, n_omega, n_c, flag;
+    int nranges, n_omega, n_c;
 };
 
 // Slot b: members of cell c0 + b, the untruncated Gaussian on them (lower
-// triangle, leading identity padding), the slot record, and the factor of the
-// first diagonal block.  status[c] becomes -level (the diagonal shift level,
+// triangle, leading identity padding to a multiple of 64), the slot record,
+// and the factor of the first 64x64 diagonal block.  status[c] becomes -level (the diagonal shift level,
 // 0 for none) and turns into the failing pivot if a factorisation step fails.
 // With retry set only the cells whose last attempt failed are rebuilt, one
 // shift level up (FP32 only).
@@ -523,7 +564,7 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
         block_ranges(a.cell_start, a.g, a.overlap, c, s.rb, s.re, &s.nranges, &s.n_omega, &s.n_c);
     __syncthreads();
     const int n_omega = s.n_omega, n_c = s.n_c, nr = s.nranges;
-    const int np = (n_omega + kNB - 1) / kNB * kNB;
+    const int np = (n_omega + kFB - 1) / kFB * kFB;
     if (tid == 0) {
         meta[slot] = int4{np, n_omega, n_c, n_c > 0 ? 1 : 0};
         lvl[slot] = level;
@@ -543,7 +584,8 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
         shift = mult[level < 4 ? level : 4] * (double)n_omega * 0x1p-24 * a.norm;
     }
     __syncthreads();
-    // wave w fills rows w, w + 4, ...; the first 32 rows also go to D
+    // wave w fills rows w, w + 4, ...; the first 64 rows also go to the
+    // diagonal block
     for (int i = wave; i < np; i += kW2) {
         T* arow = A + roff(i);
         for (int j = lane; j <= i; j += 64) {
@@ -557,20 +599,79 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
                 if (i == j) v += shift;
             }
             arow[j] = (T)v;
-            if (i < kNB) s.D[i][j] = (T)v;
+            if (i < kFB) diag64_put<T>(s.d, i, j, (T)v);
         }
     }
     __syncthreads();
-    const int f = factor_diag_block<T>(A, 0, s.D, &s.flag, lt_out + (size_t)slot * kNB * kNB);
+    const int f = factor_diag64<T>(A, 0, s.d, lt_out + (size_t)slot * kLtElems);
     if (f && tid == 0) {
         status[c] = f;
         meta[slot].w = 0;
     }
 }
 
-// Block column J: workgroup b takes the 256-row tile b / nslots_pad below the
-// diagonal block of slot b % nslots_pad.  lt_in: per slot, L_JJ transposed
-// with reciprocal pivots.
+// One step tile: rows R .. R + 16 kWS M - 1 of block column J.  The update
+// (MFMA, registers; the accumulators start from -A so that they end as the
+// negated updated tile, and the loads of A overlap the update), then the
+// panel solve x L_JJ^T = a split at the middle of L_JJ: x1 = a1 L11^-T by
+// substitution, a2 -= x1 L21^T on MFMA into the update's accumulators,
+// x2 = a2 L22^-T; both halves pass through LDS once.
+template <typename T, int M>
+__device__ __forceinline__ void step_tile(T* __restrict__ A, int J, int k0, int R, int wave,
+                                          StepLds<T>& s) {
+    constexpr int nrow = 16 * kWS * M;
+    const int lane = threadIdx.x & 63;
+    const int i16 = lane & 15, g = lane >> 4;
+    UpdateRegs<T, M> u;
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rl = 16 * (wave + kWS * t) + out_row<T>(g, v);
+                u.acc[t][cb][v] = -A[roff(R + rl) + J + 16 * cb + i16];
+            }
+    u.update(A, J, k0, R, wave);
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                s.X[16 * cb + i16][16 * (wave + kWS * t) + out_row<T>(g, v)] = -u.acc[t][cb][v];
+    __syncthreads();
+    trsm_tile<T>(s.Lt1, nrow, s.X);
+    __syncthreads();
+#pragma unroll
+    for (int s8 = 0; s8 < kNB / 4; ++s8) {
+        const int k = 4 * s8 + g;
+        const T b0 = s.L21[i16][k], b1 = s.L21[16 + i16][k];
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            const T av = s.X[k][16 * (wave + kWS * t) + i16];
+            u.acc[t][2] = mfma(av, b0, u.acc[t][2]);
+            u.acc[t][3] = mfma(av, b1, u.acc[t][3]);
+        }
+    }
+    store_tile<T>(A, J, R, nrow, s.X);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                s.X[16 * cb + i16][16 * (wave + kWS * t) + out_row<T>(g, v)] = -u.acc[t][2 + cb][v];
+    __syncthreads();
+    trsm_tile<T>(s.Lt2, nrow, s.X);
+    __syncthreads();
+    store_tile<T>(A, J + kNB, R, nrow, s.X);
+}
+
+// Block column J (64 columns): workgroup b takes the 128-row tile
+// b / nslots_pad below the diagonal block of slot b % nslots_pad.  lt_in: per
+// slot, the diagonal 32x32 blocks of L_JJ transposed with reciprocal pivots.
 template <typename T>
 __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int nslots_pad,
                                                       T* __restrict__ scratch,
@@ -580,36 +681,33 @@ __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int 
     const int slot = blockIdx.x % nslots_pad, tile = blockIdx.x / nslots_pad;
     const int4 m = meta[slot];
     const int np = m.x;
-    const int R = J + kNB + kRows2 * tile;
+    const int R = J + kFB + kRows * tile;
     if (!m.w || R >= np) return;
     const int tid = threadIdx.x;
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
-    const int nrow = np - R < kRows2 ? np - R : kRows2;
+    const T* lt = lt_in + (size_t)slot * kLtElems;
     for (int e = tid; e < kNB * kNB; e += kTS) {
         const int k = e / kNB, j = e % kNB;
-        if (j >= k) s.Lt[tri(k, j)] = lt_in[(size_t)slot * kNB * kNB + e];
+        if (j >= k) {
+            s.Lt1[tri(k, j)] = lt[e];
+            s.Lt2[tri(k, j)] = lt[kNB * kNB + e];
+        }
+        s.L21[k][j] = A[roff(J + kNB + k) + J + j];
     }
-    if (J > 0)
-        update_tile<T>(A, J, R, nrow, s.X);
+    // rows at or past the padding are zero in the padding columns
+    const int k0 = (np - m.y) / kNB * kNB;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (np - R >= kRows)
+        step_tile<T, 2>(A, J, k0, R, wave, s);
     else
-        load_tile<T>(A, J, R, nrow, s.X);
-    __syncthreads();
-    trsm_tile<T>(s.Lt, nrow, s.X);
-    __syncthreads();
-    store_tile<T>(A, J, R, nrow, s.X);
+        step_tile<T, 1>(A, J, k0, R, wave, s);
 }
 
 // Diagonal block J0 > 0 of every slot, one wave per slot: D = A[J0.., J0..] -
-// L[J0.., 0:J0] L[J0.., 0:J0]^T on its three lower 16x16 tiles (three MFMA
-// chains in one wave, operands in two register buffers, the A entries loaded
-// up front), then its Cholesky (factor_diag_block) into A and lt_out.
+// L[J0.., k0:J0] L[J0.., k0:J0]^T on its ten lower 16x16 tiles (MFMA chains,
+// operands in two register buffers), then its factor (factor_diag64) into A
+// and lt_out.
 constexpr int kDT = 64;
-
-template <typename T>
-struct DiagLds {
-    T D[kNB][kNB + 1];
-    int flag;
-};
 
 template <typename T>
 __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, int J0,
@@ -617,53 +715,58 @@ __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, 
                                                    int4* __restrict__ meta,
                                                    int* __restrict__ status,
                                                    T* __restrict__ lt_out) {
-    __shared__ DiagLds<T> s;
+    __shared__ Diag64<T> s;
     const int slot = blockIdx.x;
     const int4 m = meta[slot];
     const int np = m.x;
     if (!m.w || J0 >= np) return;
     const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
-    T d00[4], d10[4], d11[4];
+    const int k0 = (np - m.y) / kNB * kNB;
+    const T* rows[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = out_row<T>(g, v);
-        d00[v] = A[roff(J0 + r) + J0 + i16];
-        d10[v] = A[roff(J0 + 16 + r) + J0 + i16];
-        d11[v] = A[roff(J0 + 16 + r) + J0 + 16 + i16];
-    }
-    const T* r0 = A + roff(J0 + i16) + 4 * g;        // rows J0 .. J0+15
-    const T* r1 = A + roff(J0 + 16 + i16) + 4 * g;   // rows J0+16 .. J0+31
-    v4<T> t00 = {0, 0, 0, 0}, t10 = t00, t11 = t00;
-    auto mma3 = [&](const v4<T>& a0, const v4<T>& a1) {
+    for (int x = 0; x < 4; ++x) rows[x] = A + roff(J0 + 16 * x + i16) + k0 + 4 * g;
+    v4<T> acc[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) acc[t] = v4<T>{0, 0, 0, 0};
+    auto mma10 = [&](const v4<T>* b) {
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
-            t00 = mfma(a0[st], a0[st], t00);
-            t10 = mfma(a1[st], a0[st], t10);
-            t11 = mfma(a1[st], a1[st], t11);
+            int t = 0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y <= x; ++y, ++t) acc[t] = mfma(b[x][st], b[y][st], acc[t]);
         }
     };
-    const int nchunk = J0 / 16;   // even, >= 2
-    v4<T> p0 = load4(r0), p1 = load4(r1), q0, q1;
-    for (int ch = 0; ch < nchunk; ch += 2) {
-        q0 = load4(r0 + 16 * (ch + 1));
-        q1 = load4(r1 + 16 * (ch + 1));
-        mma3(p0, p1);
-        if (ch + 2 < nchunk) {
-            p0 = load4(r0 + 16 * (ch + 2));
-            p1 = load4(r1 + 16 * (ch + 2));
-        }
-        mma3(q0, q1);
-    }
+    const int nchunk = (J0 - k0) / 16;   // even, >= 2
+    v4<T> p[4], q[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = out_row<T>(g, v);
-        s.D[r][i16] = d00[v] - t00[v];
-        s.D[16 + r][i16] = d10[v] - t10[v];
-        s.D[16 + r][16 + i16] = d11[v] - t11[v];
+    for (int x = 0; x < 4; ++x) p[x] = load4(rows[x]);
+    for (int ch = 0; ch < nchunk; ch += 2) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) q[x] = load4(rows[x] + 16 * (ch + 1));
+        mma10(p);
+        if (ch + 2 < nchunk) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x) p[x] = load4(rows[x] + 16 * (ch + 2));
+        }
+        mma10(q);
+    }
+    {
+        int t = 0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y <= x; ++y, ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * x + out_row<T>(g, v), c = 16 * y + i16;
+                    diag64_put<T>(s, r, c, A[roff(J0 + r) + J0 + c] - acc[t][v]);
+                }
     }
     __syncthreads();
-    const int f = factor_diag_block<T>(A, J0, s.D, &s.flag, lt_out + (size_t)slot * kNB * kNB);
+    const int f = factor_diag64<T>(A, J0, s, lt_out + (size_t)slot * kLtElems);
     if (f && lane == 0) {
         status[c0 + slot] = f;
         meta[slot].w = 0;
@@ -842,7 +945,7 @@ static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, T* scratch, int nsl
                                  SetupProfile* prof) {
     const int pad = (nslots + 7) / 8 * 8;
     const int ncp = (a.nc_max + kZCols - 1) / kZCols;
-    T* lt_buf[2] = {lt, lt + (size_t)pad * kNB * kNB};
+    T* lt_buf[2] = {lt, lt + (size_t)pad * kLtElems};
     const int attempts = sizeof(T) == 4 ? 5 : 1;
     std::vector<int> hs;
     // every launch goes through here: with a profile, an event pair around it
@@ -877,15 +980,15 @@ static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, T* scratch, int nsl
                 k_setup_assemble<T><<<pad, kT2, 0, st>>>(a, c0, nslots, att > 0, scratch, meta,
                                                          lvl, status, lt_buf[0]);
             });
-            for (int J = 0; J + kNB < a.np_max; J += kNB) {
-                const int tiles = (a.np_max - J - kNB + kRows2 - 1) / kRows2;
-                const int b = (J / kNB) & 1;
+            for (int J = 0; J + kFB < a.np_max; J += kFB) {
+                const int tiles = (a.np_max - J - kFB + kRows - 1) / kRows;
+                const int b = (J / kFB) & 1;
                 timed(RBF_K_CHOL_STEP, [&] {
                     k_chol_step<T><<<pad * tiles, kTS, 0, st>>>(a, J, pad, scratch, meta,
                                                                 lt_buf[b]);
                 });
                 timed(RBF_K_CHOL_DIAG, [&] {
-                    k_chol_diag<T><<<pad, kDT, 0, st>>>(a, c0, J + kNB, scratch, meta, status,
+                    k_chol_diag<T><<<pad, kDT, 0, st>>>(a, c0, J + kFB, scratch, meta, status,
                                                         lt_buf[b ^ 1]);
                 });
             }
