@@ -824,23 +824,11 @@ struct ZBackLds {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kZT) void k_z_back(PrecondArgs a, long long c0, int I, int nslots_pad,
-                                                const T* __restrict__ scratch,
-                                                const int4* __restrict__ meta,
-                                                T* __restrict__ Z) {
-    __shared__ ZBackLds<T> s;
-    const int slot = blockIdx.x % nslots_pad, cp = blockIdx.x / nslots_pad;
-    const int4 m = meta[slot];
-    const int np = m.x, n_omega = m.y, n_c = m.z;
-    const int col0 = cp * kZCols;
+__device__ __forceinline__ void z_back_block(const T* __restrict__ A, T* __restrict__ Zc, int I,
+                                             int np, int n_omega, int p, int ncol, int w_lo,
+                                             ZBackLds<T>& s) {
     const int I0 = I * kNB;
-    const int p = np - n_omega;
-    if (!m.w || col0 >= n_c || I0 >= np || I0 + kNB <= p) return;
     const int lane = threadIdx.x;
-    const int ncol = n_c - col0 < kZCols ? n_c - col0 : kZCols;
-    const int w_lo = (np - n_c) / kNB * kNB;   // W is zero above this row
-    const T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
-    T* Zc = Z + a.zoff[c0 + slot] + (size_t)col0 * n_omega - p;   // Zc[c * n_omega + k]
     // W_I (zero above w_lo and in the padding rows), coalesced along each Z row
     for (int idx = lane; idx < kNB * kZCols; idx += kZT) {
         const int c = idx / kNB, r = idx % kNB;
@@ -931,6 +919,32 @@ __global__ __launch_bounds__(kZT) void k_z_back(PrecondArgs a, long long c0, int
         const int row = I0 + r;
         if (c < ncol && row >= p) Zc[(size_t)c * n_omega + row] = s.T_[r][c];
     }
+    // the next block rows read these rows back (workgroup-scope release and
+    // acquire: the same wave, the same CU)
+    __syncthreads();
+}
+
+// All block rows of the back solve for one (slot, 64 right-hand sides), from
+// the slot's last block row up, in one launch: each block row reuses the rows
+// this wave has just solved.
+template <typename T>
+__global__ __launch_bounds__(kZT, 2) void k_z_back(PrecondArgs a, long long c0, int nslots_pad,
+                                                const T* __restrict__ scratch,
+                                                const int4* __restrict__ meta,
+                                                T* __restrict__ Z) {
+    __shared__ ZBackLds<T> s;
+    const int slot = blockIdx.x % nslots_pad, cp = blockIdx.x / nslots_pad;
+    const int4 m = meta[slot];
+    const int np = m.x, n_omega = m.y, n_c = m.z;
+    const int col0 = cp * kZCols;
+    const int p = np - n_omega;
+    if (!m.w || col0 >= n_c) return;
+    const int ncol = n_c - col0 < kZCols ? n_c - col0 : kZCols;
+    const int w_lo = (np - n_c) / kNB * kNB;   // W is zero above this row
+    const T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
+    T* Zc = Z + a.zoff[c0 + slot] + (size_t)col0 * n_omega - p;   // Zc[c * n_omega + k]
+    for (int I = np / kNB - 1; I >= 0 && I * kNB + kNB > p; --I)
+        z_back_block<T>(A, Zc, I, np, n_omega, p, ncol, w_lo, s);
 }
 
 }  // namespace
@@ -996,10 +1010,9 @@ static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, T* scratch, int nsl
                 timed(RBF_K_FORWARD, [&] {
                     k_z_forward<T><<<pad * ncp, kT2, 0, st>>>(a, c0, pad, scratch, meta, Z);
                 });
-                for (int I = a.np_max / kNB - 1; I >= 0; --I)
-                    timed(RBF_K_BACK, [&] {
-                        k_z_back<T><<<pad * ncp, kZT, 0, st>>>(a, c0, I, pad, scratch, meta, Z);
-                    });
+                timed(RBF_K_BACK, [&] {
+                    k_z_back<T><<<pad * ncp, kZT, 0, st>>>(a, c0, pad, scratch, meta, Z);
+                });
             }
         }
     }

@@ -302,7 +302,7 @@ def test_error_codes(torch_dev):
 def test_setup_kernel_times(problems):
     """Event timing of the setup kernels: one assembly per batch, one step and
     one diagonal launch per 64-column block column below the first, one
-    forward solve, one back solve per 32-row block row; all times positive."""
+    forward and one back solve per batch; all times positive."""
     say("setup kernel times")
     _, P, pts, f, sigma, cutoff = problems["c0"]
     h = R.rbf_setup(pts, f, sigma, cutoff, 1)
@@ -319,5 +319,5 @@ def test_setup_kernel_times(problems):
     n = {k: v[1] for k, v in kt.items()}
     assert n["assemble"] >= 1 and n["forward"] == n["assemble"]
     assert n["chol_step"] == n["chol_diag"] and n["chol_step"] % n["assemble"] == 0
-    assert n["back"] % n["assemble"] == 0 and n["back"] >= 2 * n["chol_step"]
+    assert n["back"] == n["assemble"]
     assert all(v > 0 for v in ms.values()), ms
