@@ -357,6 +357,7 @@ struct rbf_problem {
         a.np_max = np_max;
         a.nc_max = nc_max;
         a.ncells = ncells;
+        a.xy = nullptr;
         return a;
     }
 };
@@ -649,7 +650,9 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     int* status = nullptr;
     int4* meta = nullptr;
     int* lvl = nullptr;
+    double2* xy = nullptr;
     rbf_status s = p->alloc_n(&scratch, nslots * slot_elems);
+    if (s == RBF_OK) s = p->alloc_n(&xy, pad * p->np_max);
     if (s == RBF_OK) s = p->alloc_n(&status, nc);
     if (s == RBF_OK) s = p->alloc_n(&meta, pad);
     if (s == RBF_OK) s = p->alloc_n(&lvl, pad);
@@ -660,6 +663,7 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
         if (meta) p->release(meta, st);
         if (lvl) p->release(lvl, st);
         if (lt) p->release(lt, st);
+        if (xy) p->release(xy, st);
     };
     if (s != RBF_OK) {
         p->release(Z, st);
@@ -667,6 +671,7 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
         return s;
     }
     rbf::PrecondArgs a = p->pc_args();
+    a.xy = xy;
     rbf::SetupProfile prof;
     rbf::SetupProfile* pp = p->profiling ? &prof : nullptr;
     hipError_t e;

@@ -240,20 +240,23 @@ struct UpdateRegs {
             }
         }
     }
-    // acc[t][cb] += the products (the caller initialises acc)
-    __device__ __forceinline__ void update(const T* __restrict__ A, int J, int k0, int R,
-                                           int wave) {
+    // the first loads of the update (J > 0)
+    __device__ __forceinline__ void prologue(const T* __restrict__ A, int J, int k0, int R,
+                                             int wave) {
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, g = lane >> 4;
-        if (J == 0) return;
 #pragma unroll
         for (int t = 0; t < M; ++t) arow[t] = A + roff(R + 16 * (wave + kWS * t) + i16) + k0 + 4 * g;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) brow[cb] = A + roff(J + 16 * cb + i16) + k0 + 4 * g;
-        const int nchunk = (J - k0) / 16;   // >= 2, even
         load_a(0, 0);
         load_a(1, 1);
         load_b(0, 0);
+    }
+    // acc[t][cb] += the products over (J - k0) / 16 chunks (J > 0; after the
+    // prologue; the caller initialises acc)
+    __device__ __forceinline__ void update(int J, int k0) {
+        const int nchunk = (J - k0) / 16;   // >= 2, even
         int c = 0;
         for (; c + 8 <= nchunk; c += 6) run<99>(c);
         const int rest = nchunk - c;   // 2, 4 or 6
@@ -378,6 +381,35 @@ struct Diag64 {
     T D11[kNB][kNB + 1], D21[kNB][kNB + 1], D22[kNB][kNB + 1];
     int flag;
 };
+
+// Diagonal shift mu of the FP32 retry levels (level 0: none).
+__device__ __forceinline__ double diag_shift(int level, int n_omega, double norm) {
+    if (level <= 0) return 0.0;
+    const double mult = level == 1 ? 1.0 : level == 2 ? 10.0 : level == 3 ? 100.0 : 1000.0;
+    return mult * (double)n_omega * 0x1p-24 * norm;
+}
+
+// phi(|x_i - x_j|) in FP64 (plus the shift on the diagonal), rounded once to T.
+template <typename T>
+__device__ __forceinline__ T gauss_entry(double2 pi, double2 pj, bool diag, double mk, double norm,
+                                         double shift) {
+    const double dx = pi.x - pj.x, dy = pi.y - pj.y;
+    double v = exp_neg(__builtin_fma(dx, dx, dy * dy) * mk) * norm;
+    if (diag) v += shift;
+    return (T)v;
+}
+
+// Entry (i, j) of a slot's padded local matrix: the leading p rows and
+// columns are the identity, the rest the Gaussian on the members, whose
+// coordinates xy holds in padded order.  The matrix is never stored: every
+// kernel that needs an entry evaluates it with this function, so all see the
+// same value.
+template <typename T>
+__device__ __forceinline__ T a_entry(const double2* __restrict__ xy, int p, int i, int j, double mk,
+                                     double norm, double shift) {
+    if (i < p || j < p) return (i == j) ? T(1) : T(0);
+    return gauss_entry<T>(xy[i], xy[j], i == j, mk, norm, shift);
+}
 
 template <typename T>
 struct StepLds {
@@ -524,8 +556,7 @@ __device__ void zsolve_forward(const T* __restrict__ A, int I0, int k_lo, int k_
 // (0: empty cell, beyond the last cell, or a failed pivot).
 template <typename T>
 struct AssembleLds {
-    double mx[RBF_MAX_BLOCK];
-    double my[RBF_MAX_BLOCK];
+    double2 mxy[kFB];         // coordinates of the first 64 members (padded order)
     Diag64<T> d;
     int rb[kMaxRanges], re[kMaxRanges];
     int nranges, n_omega, n_c;
@@ -573,35 +604,24 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
     if (n_c == 0) return;
     const int p = np - n_omega;
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
+    double2* xy = a.xy + (size_t)slot * a.np_max;
     for (int k = tid; k < n_omega; k += kT2) {
         const int m = member_index(s.rb, s.re, nr, k);
-        s.mx[k] = a.xs[m];
-        s.my[k] = a.ys[m];
+        const double2 q = {a.xs[m], a.ys[m]};
+        if (p + k < kFB) s.mxy[p + k] = q;
+        xy[p + k] = q;
     }
-    double shift = 0.0;
-    if (level > 0) {
-        const double mult[5] = {0.0, 1.0, 10.0, 100.0, 1000.0};
-        shift = mult[level < 4 ? level : 4] * (double)n_omega * 0x1p-24 * a.norm;
-    }
+    const double shift = diag_shift(level, n_omega, a.norm);
     __syncthreads();
-    // wave w fills rows w, w + 4, ...; the first 64 rows also go to the
-    // diagonal block
-    for (int i = wave; i < np; i += kW2) {
-        T* arow = A + roff(i);
+    // the first 64x64 diagonal block (the rest of the matrix is evaluated
+    // where it is used)
+    for (int i = wave; i < kFB; i += kW2)
         for (int j = lane; j <= i; j += 64) {
-            double v;
-            if (i < p || j < p) {
-                v = (i == j) ? 1.0 : 0.0;
-            } else {
-                const double dx = s.mx[i - p] - s.mx[j - p];
-                const double dy = s.my[i - p] - s.my[j - p];
-                v = exp_neg(__builtin_fma(dx, dx, dy * dy) * a.mk) * a.norm;
-                if (i == j) v += shift;
-            }
-            arow[j] = (T)v;
-            if (i < kFB) diag64_put<T>(s.d, i, j, (T)v);
+            const T v = (i < p || j < p) ? T(i == j ? 1 : 0)
+                                         : gauss_entry<T>(s.mxy[i], s.mxy[j], i == j, a.mk, a.norm,
+                                                          shift);
+            diag64_put<T>(s.d, i, j, v);
         }
-    }
     __syncthreads();
     const int f = factor_diag64<T>(A, 0, s.d, lt_out + (size_t)slot * kLtElems);
     if (f && tid == 0) {
@@ -617,7 +637,8 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
 // substitution, a2 -= x1 L21^T on MFMA into the update's accumulators,
 // x2 = a2 L22^-T; both halves pass through LDS once.
 template <typename T, int M>
-__device__ __forceinline__ void step_tile(T* __restrict__ A, int J, int k0, int R, int wave,
+__device__ __forceinline__ void step_tile(T* __restrict__ A, const double2* __restrict__ xy, int p,
+                                          double mk, double norm, int J, int k0, int R, int wave,
                                           StepLds<T>& s) {
     constexpr int nrow = 16 * kWS * M;
     const int lane = threadIdx.x & 63;
@@ -626,20 +647,21 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, int J, int k0, int 
 #pragma unroll
     for (int t = 0; t < M; ++t)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rl = 16 * (wave + kWS * t) + out_row<T>(g, v);
-                u.acc[t][cb][v] = -A[roff(R + rl) + J + 16 * cb + i16];
-            }
-    u.update(A, J, k0, R, wave);
+        for (int cb = 0; cb < 4; ++cb) u.acc[t][cb] = v4<T>{0, 0, 0, 0};
+    if (J > 0) {
+        u.prologue(A, J, k0, R, wave);
+        u.update(J, k0);
+    }
 #pragma unroll
     for (int t = 0; t < M; ++t)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                s.X[16 * cb + i16][16 * (wave + kWS * t) + out_row<T>(g, v)] = -u.acc[t][cb][v];
+            for (int v = 0; v < 4; ++v) {
+                const int rl = 16 * (wave + kWS * t) + out_row<T>(g, v);
+                const int col = 16 * cb + i16;
+                s.X[col][rl] = a_entry<T>(xy, p, R + rl, J + col, mk, norm, 0.0) - u.acc[t][cb][v];
+            }
     __syncthreads();
     trsm_tile<T>(s.Lt1, nrow, s.X);
     __syncthreads();
@@ -661,8 +683,12 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, int J, int k0, int 
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                s.X[16 * cb + i16][16 * (wave + kWS * t) + out_row<T>(g, v)] = -u.acc[t][2 + cb][v];
+            for (int v = 0; v < 4; ++v) {
+                const int rl = 16 * (wave + kWS * t) + out_row<T>(g, v);
+                const int col = 16 * cb + i16;
+                s.X[col][rl] = a_entry<T>(xy, p, R + rl, J + kNB + col, mk, norm, 0.0) -
+                               u.acc[t][2 + cb][v];
+            }
     __syncthreads();
     trsm_tile<T>(s.Lt2, nrow, s.X);
     __syncthreads();
@@ -697,10 +723,12 @@ __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int 
     // rows at or past the padding are zero in the padding columns
     const int k0 = (np - m.y) / kNB * kNB;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double2* xy = a.xy + (size_t)slot * a.np_max;
+    const int p = np - m.y;
     if (np - R >= kRows)
-        step_tile<T, 2>(A, J, k0, R, wave, s);
+        step_tile<T, 2>(A, xy, p, a.mk, a.norm, J, k0, R, wave, s);
     else
-        step_tile<T, 1>(A, J, k0, R, wave, s);
+        step_tile<T, 1>(A, xy, p, a.mk, a.norm, J, k0, R, wave, s);
 }
 
 // Diagonal block J0 > 0 of every slot, one wave per slot: D = A[J0.., J0..] -
@@ -713,6 +741,7 @@ template <typename T>
 __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, int J0,
                                                    T* __restrict__ scratch,
                                                    int4* __restrict__ meta,
+                                                   const int* __restrict__ lvl,
                                                    int* __restrict__ status,
                                                    T* __restrict__ lt_out) {
     __shared__ Diag64<T> s;
@@ -723,6 +752,9 @@ __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, 
     const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
     const int k0 = (np - m.y) / kNB * kNB;
+    const int pad_rows = np - m.y;
+    const double2* xy = a.xy + (size_t)slot * a.np_max;
+    const double shift = sizeof(T) == 4 ? diag_shift(lvl[slot], m.y, a.norm) : 0.0;
     const T* rows[4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) rows[x] = A + roff(J0 + 16 * x + i16) + k0 + 4 * g;
@@ -762,7 +794,8 @@ __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * x + out_row<T>(g, v), c = 16 * y + i16;
-                    diag64_put<T>(s, r, c, A[roff(J0 + r) + J0 + c] - acc[t][v]);
+                    diag64_put<T>(s, r, c,
+                                  a_entry<T>(xy, pad_rows, J0 + r, J0 + c, a.mk, a.norm, shift) - acc[t][v]);
                 }
     }
     __syncthreads();
@@ -1002,8 +1035,8 @@ static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, T* scratch, int nsl
                                                                 lt_buf[b]);
                 });
                 timed(RBF_K_CHOL_DIAG, [&] {
-                    k_chol_diag<T><<<pad, kDT, 0, st>>>(a, c0, J + kFB, scratch, meta, status,
-                                                        lt_buf[b ^ 1]);
+                    k_chol_diag<T><<<pad, kDT, 0, st>>>(a, c0, J + kFB, scratch, meta, lvl,
+                                                        status, lt_buf[b ^ 1]);
                 });
             }
             if (ncp > 0) {

@@ -136,10 +136,12 @@ struct PrecondArgs {
     int np_max;             // padded block size bound (multiple of 64)
     int nc_max;             // largest number of points in one cell
     long long ncells;
+    double2* xy;            // setup only: per batch slot, np_max member coordinates
+                            // (padded order; the padding rows unused)
 };
 // Build Z_c (centre rows of the inverse of the local matrix) for all cells, in
-// batches of nslots cells.  scratch holds nslots * slot_elems64(np_max)
-// elements, meta and lvl 8 * ceil(nslots / 8) entries, lt 2 * 2048 * 8 *
+// batches of nslots cells.  a.xy holds 8 * ceil(nslots / 8) * np_max entries,
+// scratch nslots * slot_elems64(np_max) elements, meta and lvl 8 * ceil(nslots / 8) entries, lt 2 * 2048 * 8 *
 // ceil(nslots / 8) elements.  status[c]: 0 ok, -k after the k-th diagonal
 // shift level (FP32 only), > 0 the failing pivot (1-based).
 __host__ __device__ inline long long slot_elems64(int np_max) {
