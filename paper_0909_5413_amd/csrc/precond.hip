@@ -412,10 +412,24 @@ __device__ __forceinline__ T a_entry(const double2* __restrict__ xy, int p, int 
 }
 
 template <typename T>
+struct StepLds;
+
+// Entry (R + rl, J + c) of a slot's padded local matrix, J + c < R, from the
+// coordinates a step tile staged in LDS (same value as a_entry).
+template <typename T>
+__device__ __forceinline__ T lds_entry(const StepLds<T>& s, int p, int R, int J, int rl, int c,
+                                       double mk, double norm) {
+    if (J + c < p) return T(0);
+    return gauss_entry<T>(s.xr[rl], s.xc[c], false, mk, norm, 0.0);
+}
+
+template <typename T>
 struct StepLds {
     T X[kNB][kXS];            // 32 columns of the tile's rows, one column per thread
     T Lt1[kTri], Lt2[kTri];   // diagonal 32x32 blocks of L_JJ transposed (packed), reciprocal pivots
     T L21[kNB][kNB + 1];      // L21[j][k] = L[J + 32 + j][J + k]
+    double2 xr[kRows];        // member coordinates of the tile's rows
+    double2 xc[kFB];          // and of the block column's 64 columns
 };
 
 template <typename T>
@@ -652,6 +666,7 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const double2* __re
         u.prologue(A, J, k0, R, wave);
         u.update(J, k0);
     }
+    __syncthreads();   // the staged coordinates
 #pragma unroll
     for (int t = 0; t < M; ++t)
 #pragma unroll
@@ -660,7 +675,7 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const double2* __re
             for (int v = 0; v < 4; ++v) {
                 const int rl = 16 * (wave + kWS * t) + out_row<T>(g, v);
                 const int col = 16 * cb + i16;
-                s.X[col][rl] = a_entry<T>(xy, p, R + rl, J + col, mk, norm, 0.0) - u.acc[t][cb][v];
+                s.X[col][rl] = lds_entry<T>(s, p, R, J, rl, col, mk, norm) - u.acc[t][cb][v];
             }
     __syncthreads();
     trsm_tile<T>(s.Lt1, nrow, s.X);
@@ -686,7 +701,7 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const double2* __re
             for (int v = 0; v < 4; ++v) {
                 const int rl = 16 * (wave + kWS * t) + out_row<T>(g, v);
                 const int col = 16 * cb + i16;
-                s.X[col][rl] = a_entry<T>(xy, p, R + rl, J + kNB + col, mk, norm, 0.0) -
+                s.X[col][rl] = lds_entry<T>(s, p, R, J, rl, kNB + col, mk, norm) -
                                u.acc[t][2 + cb][v];
             }
     __syncthreads();
@@ -720,6 +735,12 @@ __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int 
         }
         s.L21[k][j] = A[roff(J + kNB + k) + J + j];
     }
+    {
+        const double2* xy = a.xy + (size_t)slot * a.np_max;
+        const int nrow = np - R < kRows ? np - R : kRows;
+        if (tid < nrow) s.xr[tid] = xy[R + tid];
+        if (tid < kFB) s.xc[tid] = xy[J + tid];
+    }
     // rows at or past the padding are zero in the padding columns
     const int k0 = (np - m.y) / kNB * kNB;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -752,8 +773,8 @@ __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, 
     const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
     const int k0 = (np - m.y) / kNB * kNB;
-    const int pad_rows = np - m.y;
-    const double2* xy = a.xy + (size_t)slot * a.np_max;
+    __shared__ double2 xd[kFB];   // coordinates of the block's 64 rows
+    xd[lane] = a.xy[(size_t)slot * a.np_max + J0 + lane];
     const double shift = sizeof(T) == 4 ? diag_shift(lvl[slot], m.y, a.norm) : 0.0;
     const T* rows[4];
 #pragma unroll
@@ -785,6 +806,7 @@ __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, 
         }
         mma10(q);
     }
+    __syncthreads();   // the staged coordinates
     {
         int t = 0;
 #pragma unroll
@@ -794,8 +816,10 @@ __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * x + out_row<T>(g, v), c = 16 * y + i16;
+                    // rows J0 + r >= 64 lie past the padding (fewer than 64 rows)
                     diag64_put<T>(s, r, c,
-                                  a_entry<T>(xy, pad_rows, J0 + r, J0 + c, a.mk, a.norm, shift) - acc[t][v]);
+                                  gauss_entry<T>(xd[r], xd[c], r == c, a.mk, a.norm, shift) -
+                                      acc[t][v]);
                 }
     }
     __syncthreads();
