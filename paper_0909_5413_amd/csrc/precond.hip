@@ -727,13 +727,25 @@ __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int 
     const int tid = threadIdx.x;
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
     const T* lt = lt_in + (size_t)slot * kLtElems;
-    for (int e = tid; e < kNB * kNB; e += kTS) {
-        const int k = e / kNB, j = e % kNB;
-        if (j >= k) {
-            s.Lt1[tri(k, j)] = lt[e];
-            s.Lt2[tri(k, j)] = lt[kNB * kNB + e];
+    {
+        constexpr int kE = kNB * kNB / kTS;
+        T l1[kE], l2[kE], l21[kE];
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const int e = tid + kTS * q, k = e / kNB, j = e % kNB;
+            l1[q] = lt[e];
+            l2[q] = lt[kNB * kNB + e];
+            l21[q] = A[roff(J + kNB + k) + J + j];
         }
-        s.L21[k][j] = A[roff(J + kNB + k) + J + j];
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const int e = tid + kTS * q, k = e / kNB, j = e % kNB;
+            if (j >= k) {
+                s.Lt1[tri(k, j)] = l1[q];
+                s.Lt2[tri(k, j)] = l2[q];
+            }
+            s.L21[k][j] = l21[q];
+        }
     }
     {
         const double2* xy = a.xy + (size_t)slot * a.np_max;
