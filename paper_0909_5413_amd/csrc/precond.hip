@@ -883,7 +883,7 @@ __global__ __launch_bounds__(kT2, 2) void k_z_forward(PrecondArgs a, long long c
 // each loaded once, the next chunk of 16 k in flight; W_I and the result move
 // through LDS with coalesced accesses, and the 32x32 triangular solve runs one
 // right-hand side per lane, unrolled in registers.
-constexpr int kZT = 64;   // threads of the back-solve kernel (one wave)
+constexpr int kZT = 128;   // threads of the back-solve kernel (two waves)
 
 template <typename T>
 struct ZBackLds {
@@ -897,35 +897,37 @@ __device__ __forceinline__ void z_back_block(const T* __restrict__ A, T* __restr
                                              int np, int n_omega, int p, int ncol, int w_lo,
                                              ZBackLds<T>& s) {
     const int I0 = I * kNB;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // W_I (zero above w_lo and in the padding rows), coalesced along each Z row
-    for (int idx = lane; idx < kNB * kZCols; idx += kZT) {
+    for (int idx = tid; idx < kNB * kZCols; idx += kZT) {
         const int c = idx / kNB, r = idx % kNB;
         const int row = I0 + r;
         s.T_[r][c] = (c < ncol && row >= w_lo && row >= p) ? Zc[(size_t)c * n_omega + row] : T(0);
     }
-    for (int idx = lane; idx < kNB * kNB; idx += kZT) {
+    for (int idx = tid; idx < kNB * kNB; idx += kZT) {
         const int i = idx / kNB, j = idx % kNB;
         s.L[i][j] = (j <= i) ? A[roff(I0 + i) + I0 + j] : T(0);
     }
-    // product over k in [I0 + 32, np)
+    // product over k in [I0 + 32, np); wave w the right-hand sides 32w ..
     const int i16 = lane & 15, g = lane >> 4;
     const int nchunk = (np - I0 - kNB) / 16;   // even
-    v4<T> acc[2][4];
+    v4<T> acc[2][2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = v4<T>{0, 0, 0, 0};
+        for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = v4<T>{0, 0, 0, 0};
     if (nchunk > 0) {
-        const T* zr[4];
-        bool zv[4];
+        const T* zr[2];
+        bool zv[2];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            zv[ct] = 16 * ct + i16 < ncol;
-            zr[ct] = Zc + (size_t)(zv[ct] ? 16 * ct + i16 : 0) * n_omega;
+        for (int ct = 0; ct < 2; ++ct) {
+            const int c = 32 * wave + 16 * ct + i16;
+            zv[ct] = c < ncol;
+            zr[ct] = Zc + (size_t)(zv[ct] ? c : 0) * n_omega;
         }
         struct Buf {
-            T a[2][4], b[4][4];
+            T a[2][4], b[2][4];
         } q0, q1;
         auto load = [&](Buf& d, int ch) {
             const int k = I0 + kNB + 16 * ch + 4 * g;
@@ -936,40 +938,40 @@ __device__ __forceinline__ void z_back_block(const T* __restrict__ A, T* __restr
                 d.a[1][st] = lr[16];
             }
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
+            for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
                 for (int st = 0; st < 4; ++st) d.b[ct][st] = zv[ct] ? zr[ct][k + st] : T(0);
         };
-        auto mma8 = [&](const Buf& d) {
+        auto mma4 = [&](const Buf& d) {
 #pragma unroll
             for (int st = 0; st < 4; ++st)
 #pragma unroll
                 for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-                    for (int ct = 0; ct < 4; ++ct)
+                    for (int ct = 0; ct < 2; ++ct)
                         acc[rt][ct] = mfma(d.a[rt][st], d.b[ct][st], acc[rt][ct]);
         };
         // two register buffers in turn (nchunk is even)
         load(q0, 0);
         for (int ch = 0; ch < nchunk; ch += 2) {
             load(q1, ch + 1);
-            mma8(q0);
+            mma4(q0);
             if (ch + 2 < nchunk) load(q0, ch + 2);
-            mma8(q1);
+            mma4(q1);
         }
     }
     __syncthreads();
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
+        for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                s.T_[16 * rt + out_row<T>(g, v)][16 * ct + i16] -= acc[rt][ct][v];
-    if (lane < kNB) s.invd[lane] = T(1) / s.L[lane][lane];
+                s.T_[16 * rt + out_row<T>(g, v)][32 * wave + 16 * ct + i16] -= acc[rt][ct][v];
+    if (tid < kNB) s.invd[tid] = T(1) / s.L[tid][tid];
     __syncthreads();
-    // L_II^T x = t for right-hand side `lane`, from the last row up
-    {
+    // L_II^T x = t for right-hand side `lane` (wave 0), from the last row up
+    if (wave == 0) {
         T x[kNB];
 #pragma unroll
         for (int r = 0; r < kNB; ++r) x[r] = s.T_[r][lane];
@@ -983,7 +985,7 @@ __device__ __forceinline__ void z_back_block(const T* __restrict__ A, T* __restr
         for (int r = 0; r < kNB; ++r) s.T_[r][lane] = x[r];
     }
     __syncthreads();
-    for (int idx = lane; idx < kNB * kZCols; idx += kZT) {
+    for (int idx = tid; idx < kNB * kZCols; idx += kZT) {
         const int c = idx / kNB, r = idx % kNB;
         const int row = I0 + r;
         if (c < ncol && row >= p) Zc[(size_t)c * n_omega + row] = s.T_[r][c];
@@ -997,7 +999,7 @@ __device__ __forceinline__ void z_back_block(const T* __restrict__ A, T* __restr
 // the slot's last block row up, in one launch: each block row reuses the rows
 // this wave has just solved.
 template <typename T>
-__global__ __launch_bounds__(kZT, 2) void k_z_back(PrecondArgs a, long long c0, int nslots_pad,
+__global__ __launch_bounds__(kZT, 3) void k_z_back(PrecondArgs a, long long c0, int nslots_pad,
                                                 const T* __restrict__ scratch,
                                                 const int4* __restrict__ meta,
                                                 T* __restrict__ Z) {
