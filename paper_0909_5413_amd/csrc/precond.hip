@@ -292,26 +292,59 @@ __device__ void store_tile(T* __restrict__ A, int J, int R, int nrow, T (*X)[kXS
     }
 }
 
-// Row tid of the tile: x L_DD^T = a in place (column tid of X) for a 32x32
-// diagonal block D of L_JJ, column by column so that every step is 31 - k
-// independent FMAs.  Lt holds L_DD transposed (Lt[k][j] = L[j][k], j > k)
-// with the reciprocal pivots on its diagonal; every lane reads the same Lt
-// entries (LDS broadcasts).
-template <typename T>
-__device__ __forceinline__ void trsm_tile(const T* Lt, int nrow, T (*X)[kXS]) {
-    const int tid = threadIdx.x;
-    if (tid >= nrow) return;
-    T x[kNB];
+// Rows of the tile: x L_DD^T = a in place (thread tid: column tid of X) for
+// a 32x32 diagonal block D of L_JJ, split at column 16: the first 16 columns
+// by substitution (column by column, 15 - k independent FMAs at step k), the
+// last 16 updated by one MFMA pass, x[16..31] -= x[0..15] L[16..31][0..15]^T
+// (each wave its row tiles), then their substitution.  Lt holds L_DD
+// transposed and packed (Lt[tri(k, j)] = L[j][k], j > k) with the reciprocal
+// pivots on its diagonal; every lane reads the same Lt entries (LDS
+// broadcasts).  Ends with a barrier.
+template <typename T, int M>
+__device__ __forceinline__ void trsm_tile(const T* Lt, int wave, T (*X)[kXS]) {
+    constexpr int nrow = 16 * kWS * M, kH = kNB / 2;
+    const int tid = threadIdx.x, lane = tid & 63, i16 = lane & 15, g = lane >> 4;
+    if (tid < nrow) {
+        T x[kH];
 #pragma unroll
-    for (int q = 0; q < kNB; ++q) x[q] = X[q][tid];
+        for (int q = 0; q < kH; ++q) x[q] = X[q][tid];
 #pragma unroll
-    for (int k = 0; k < kNB; ++k) {
-        x[k] *= Lt[tri(k, k)];
+        for (int k = 0; k < kH; ++k) {
+            x[k] *= Lt[tri(k, k)];
 #pragma unroll
-        for (int j = k + 1; j < kNB; ++j) x[j] = fma_t(-x[k], Lt[tri(k, j)], x[j]);
+            for (int j = k + 1; j < kH; ++j) x[j] = fma_t(-x[k], Lt[tri(k, j)], x[j]);
+        }
+#pragma unroll
+        for (int q = 0; q < kH; ++q) X[q][tid] = x[q];
     }
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kNB; ++q) X[q][tid] = x[q];
+    for (int t = 0; t < M; ++t) {
+        const int rt = wave + kWS * t;
+        v4<T> d = {0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < kH / 4; ++s4) {
+            const int k = 4 * s4 + g;
+            d = mfma(X[k][16 * rt + i16], Lt[tri(k, kH + i16)], d);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[kH + i16][16 * rt + out_row<T>(g, v)] -= d[v];
+    }
+    __syncthreads();
+    if (tid < nrow) {
+        T x[kH];
+#pragma unroll
+        for (int q = 0; q < kH; ++q) x[q] = X[kH + q][tid];
+#pragma unroll
+        for (int k = 0; k < kH; ++k) {
+            x[k] *= Lt[tri(kH + k, kH + k)];
+#pragma unroll
+            for (int j = k + 1; j < kH; ++j) x[j] = fma_t(-x[k], Lt[tri(kH + k, kH + j)], x[j]);
+        }
+#pragma unroll
+        for (int q = 0; q < kH; ++q) X[kH + q][tid] = x[q];
+    }
+    __syncthreads();
 }
 
 // Factor the 64x32 panel at J0 (rows J0 .. J0 + 63, columns J0 .. J0 + 31):
@@ -678,8 +711,7 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const double2* __re
                 s.X[col][rl] = lds_entry<T>(s, p, R, J, rl, col, mk, norm) - u.acc[t][cb][v];
             }
     __syncthreads();
-    trsm_tile<T>(s.Lt1, nrow, s.X);
-    __syncthreads();
+    trsm_tile<T, M>(s.Lt1, wave, s.X);
 #pragma unroll
     for (int s8 = 0; s8 < kNB / 4; ++s8) {
         const int k = 4 * s8 + g;
@@ -705,8 +737,7 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const double2* __re
                                u.acc[t][2 + cb][v];
             }
     __syncthreads();
-    trsm_tile<T>(s.Lt2, nrow, s.X);
-    __syncthreads();
+    trsm_tile<T, M>(s.Lt2, wave, s.X);
     store_tile<T>(A, J + kNB, R, nrow, s.X);
 }
 
