@@ -1,0 +1,223 @@
+"""Edge cases of the GPU path, through the C ABI (-m gpu).
+
+Degenerate problems against closed forms: one point (lambda = f / phi(0)),
+two points (the 2x2 system), one cell holding every point (the restricted
+additive Schwarz preconditioner is then the exact inverse, so right-
+preconditioned GMRES stops after one iteration, Section 2.2).  A point set
+with empty cells (an annulus: cells with no own points build no block and
+own no rows), and the largest local blocks the workloads here reach (local
+blocks of up to 1444 points, n_p = 1472: 23 block columns of the
+factorisation; up to 169 points per cell: three passes of 64 right-hand
+sides in the centre-row solves), each against the oracle.  A local block
+above RBF_MAX_BLOCK is refused with RBF_ELIMIT.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_0909_5413_amd as R
+from paper_0909_5413_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.lib()
+    return torch
+
+
+def lattice(n, h_over_sigma, seed, jitter=0.1):
+    rng = np.random.default_rng(seed)
+    h = 2.0 / n
+    xs = -1 + (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(xs, xs)
+    pts = np.stack([X.ravel(), Y.ravel()], 1) + rng.uniform(-jitter * h, jitter * h, (n * n, 2))
+    return pts, h / h_over_sigma
+
+
+def annulus():
+    pts, sigma = lattice(40, 0.9, 21)
+    r = np.hypot(pts[:, 0], pts[:, 1])
+    return pts[(r > 0.55) & (r < 1.0)], sigma, 6 * sigma
+
+
+def largest_blocks():
+    pts, sigma = lattice(60, 0.95, 22)
+    return pts, sigma, 12 * sigma
+
+
+def gpu_matvec(torch, h, w):
+    dw = torch.tensor(w, device="cuda", dtype=torch.float64)
+    dy = torch.empty_like(dw)
+    R.rbf_matvec_device(h, dw, dy, R.RBF_FP64, R.RBF_ORDER_ORIGINAL, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return dy.cpu().numpy()
+
+
+def gpu_rasm(torch, h, v):
+    dv = torch.tensor(v, device="cuda", dtype=torch.float64)
+    dz = torch.empty_like(dv)
+    R.rbf_precond_apply_device(h, dv, dz, R.RBF_FP64, R.RBF_ORDER_ORIGINAL,
+                               torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return dz.cpu().numpy()
+
+
+def test_single_point(torch_dev):
+    say("one point")
+    sigma, f = 0.1, np.array([2.0])
+    h = R.rbf_setup(np.array([[0.3, -0.2]]), f, sigma, 6 * sigma, 1)
+    try:
+        for prec, rtol in ((R.RBF_FP64, 1e-14), (R.RBF_MIXED, 1e-12)):
+            lam, info, st = R.rbf_solve(h, 1, R.default_opts(rtol=rtol, precision=prec))
+            assert st == R.RBF_OK
+            # A = [phi(0)] = [1 / (2 pi sigma^2)]
+            assert abs(lam[0] - f[0] * 2 * np.pi * sigma * sigma) <= rtol * abs(lam[0])
+    finally:
+        R.rbf_destroy(h)
+
+
+def test_two_points(torch_dev):
+    say("two points")
+    sigma = 0.1
+    pts = np.array([[0.0, 0.0], [0.05, 0.02]])
+    f = np.array([1.0, -0.5])
+    h = R.rbf_setup(pts, f, sigma, 6 * sigma, 1)
+    try:
+        lam, info, st = R.rbf_solve(h, 2, R.default_opts(rtol=1e-14))
+    finally:
+        R.rbf_destroy(h)
+    d2 = float(np.sum((pts[0] - pts[1]) ** 2))
+    e = np.exp(-d2 / (2 * sigma * sigma))
+    A = np.array([[1.0, e], [e, 1.0]]) / (2 * np.pi * sigma * sigma)
+    ref = np.linalg.solve(A, f)
+    assert np.linalg.norm(lam - ref) <= 1e-13 * np.linalg.norm(ref), (lam, ref)
+    assert info.iterations == 1
+
+
+def test_single_subdomain(torch_dev, oracle_mod):
+    """Every point in one cell: M^-1 = A^-1, so one GMRES iteration reaches
+    cond(A) u, far below the tolerance on a jittered lattice at h/sigma = 1."""
+    say("one cell")
+    rng = np.random.default_rng(3)
+    sigma = 0.02
+    xs = (np.arange(12) - 5.5) * sigma
+    X, Y = np.meshgrid(xs, xs)
+    pts = np.stack([X.ravel(), Y.ravel()], 1) + rng.uniform(-0.1 * sigma, 0.1 * sigma, (144, 2))
+    f = W.gaussian_vortex(pts)
+    h = R.rbf_setup(pts, f, sigma, 60 * sigma, 1)
+    try:
+        _, (ncx, ncy) = R.rbf_grid(h)
+        assert (ncx, ncy) == (1, 1)
+        lam, info, st = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-12))
+    finally:
+        R.rbf_destroy(h)
+    assert info.iterations == 1
+    P = oracle_mod.Problem(pts, sigma, 60 * sigma, 1)
+    try:
+        assert P.rel_residual(f, lam) <= 1e-12
+    finally:
+        P.close()
+
+
+def test_empty_cells(torch_dev, oracle_mod):
+    """An annulus: the cells inside the hole have no points."""
+    pts, sigma, cutoff = annulus()
+    say("annulus", pts.shape[0])
+    f = W.gaussian_vortex(pts)
+    h = R.rbf_setup(pts, f, sigma, cutoff, 1)
+    P = oracle_mod.Problem(pts, sigma, cutoff, 1)
+    try:
+        _, (ncx, ncy) = R.rbf_grid(h)
+        cell_of, perm, cs = R.rbf_binning(h, pts.shape[0])
+        o_cell, o_perm, o_cs = P.binning()
+        assert np.array_equal(cell_of, o_cell) and np.array_equal(perm, o_perm)
+        assert np.array_equal(cs.astype(np.int64), o_cs)
+        assert int(np.sum(np.diff(o_cs) == 0)) >= 1, "the annulus has empty cells"
+        w = W.random_weights(pts.shape[0], 31)
+        y = gpu_matvec(torch_dev, h, w)
+        assert np.max(np.abs(y - P.matvec(w)) / P.matvec(np.abs(w))) <= 1e-13
+        P.rasm_setup()
+        z = gpu_rasm(torch_dev, h, w)
+        zo = P.rasm_apply(w)
+        assert np.linalg.norm(z - zo) <= 1e-7 * np.linalg.norm(zo)
+        lam, info, st = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-12))
+        assert P.rel_residual(f, lam) <= 1.05e-12
+        _, oinfo = P.gmres(f, 30, 1e-12)
+        assert abs(info.iterations - oinfo.iterations) <= 2
+    finally:
+        R.rbf_destroy(h)
+        P.close()
+
+
+def test_largest_blocks(torch_dev, oracle_mod):
+    """Local blocks of up to 1444 points (n_p = 1472) and cells of up to 169
+    points: the centre rows of the largest block are backward-stable rows of
+    its inverse, the RASM apply and the FP64 and mixed solves match the
+    oracle."""
+    pts, sigma, cutoff = largest_blocks()
+    say("largest blocks", pts.shape[0])
+    from tests import bruteforce as bf
+    f = W.gaussian_vortex(pts)
+    h = R.rbf_setup(pts, f, sigma, cutoff, 1)
+    P = oracle_mod.Problem(pts, sigma, cutoff, 1)
+    try:
+        _, (ncx, ncy) = R.rbf_grid(h)
+        _, _, o_cs = P.binning()
+        own = np.diff(o_cs)
+        sizes = []
+        for cell in range(ncx * ncy):
+            mem, _, _ = P.rasm_block(cell, with_factor=False)
+            sizes.append(len(mem))
+        big = int(np.argmax(sizes))
+        assert sizes[big] > 1400 and own.max() > 128, (sizes[big], own.max())
+        u = np.finfo(float).eps / 2
+        for cell in (big, int(np.argmax(own))):
+            mem, Z = R.rbf_precond_block(h, cell, R.RBF_FP64)
+            o_mem, kc, _ = P.rasm_block(cell, with_factor=False)
+            assert np.array_equal(mem, o_mem)
+            A = bf.dense_matrix(pts[mem], sigma, None)
+            n = len(mem)
+            E = np.eye(n)[n - kc:]
+            res = np.linalg.norm(Z @ A - E, 2)
+            bound = 10 * n * u * np.linalg.norm(Z, 2) * np.linalg.norm(A, 2)
+            say("largest block", cell, n, kc, res / bound)
+            assert res <= bound, (cell, res, bound)
+        P.rasm_setup()
+        v = W.random_weights(pts.shape[0], 41)
+        z = gpu_rasm(torch_dev, h, v)
+        zo = P.rasm_apply(v)
+        assert np.linalg.norm(z - zo) <= 1e-7 * np.linalg.norm(zo)
+        lam, info, st = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-12))
+        assert P.rel_residual(f, lam) <= 1.05e-12
+        _, oinfo = P.gmres(f, 30, 1e-12)
+        assert abs(info.iterations - oinfo.iterations) <= 2
+        lam32, info32, st32 = R.rbf_solve(h, pts.shape[0],
+                                          R.default_opts(rtol=1e-12, precision=R.RBF_MIXED))
+        assert st32 == R.RBF_OK and P.rel_residual(f, lam32) <= 1.05e-12
+    finally:
+        R.rbf_destroy(h)
+        P.close()
+
+
+def test_block_limit(torch_dev):
+    """A local block above RBF_MAX_BLOCK points is refused, not truncated."""
+    pts, sigma = lattice(50, 0.9, 23)
+    say("block limit", pts.shape[0])
+    f = W.gaussian_vortex(pts)
+    h = R.rbf_setup(pts, f, sigma, 13 * sigma, 1)
+    try:
+        with pytest.raises(R.RbfError) as e:
+            R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-10))
+        assert e.value.status == R.RBF_ELIMIT
+    finally:
+        R.rbf_destroy(h)
