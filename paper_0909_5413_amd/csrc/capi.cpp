@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -27,6 +28,7 @@
 using rbf::Grid;
 
 static constexpr double kPi = 3.14159265358979323846;
+static constexpr long double kLn2L = 0.693147180559945309417232121458176568L;
 
 namespace {
 
@@ -327,6 +329,7 @@ struct rbf_problem {
         a.g = g;
         a.rc2 = cutoff * cutoff;
         a.mk = -1.0 / (2.0 * sigma * sigma);
+        a.beta = (double)(-16.0L / ((long double)sigma * (long double)sigma * kLn2L));
         a.norm = 1.0 / (2.0 * kPi * sigma * sigma);
         a.etab = etab;
         a.ntab = ntab;
@@ -400,37 +403,83 @@ rbf_status check_args(long long n, double sigma, double cutoff, int overlap) {
 // The setup pipeline on device arrays d_pts (n x 2) and d_vals (n or NULL).
 // Neighbour lists of the matvec (skipped when some 3x3 block of cells holds
 // more sources than a list-driven launch can stage; the candidate kernels then
-// serve every matvec).
+// serve every matvec).  Groups run along cell rows: a group takes consecutive
+// cells of one row while it spans at most kGroupCells columns, stages at most
+// kGroupSpan sources and holds at most kGroupMaxUnits units of 64 targets; a
+// cell with more targets than that is split over several groups.
 rbf_status build_lists(rbf_problem* p, hipStream_t st) {
     const rbf::Grid& g = p->g;
-    const long long nc = p->ncells;
-    std::vector<int2> units;
-    int max_nb = 0;
-    for (long long c = 0; c < nc; ++c) {
-        const int own = p->cs_host[c + 1] - p->cs_host[c];
-        if (own == 0) continue;
-        const int cx = (int)(c % g.ncx), cy = (int)(c / g.ncx);
-        const int xlo = std::max(cx - 1, 0), xhi = std::min(cx + 1, g.ncx - 1);
-        long long nb = 0;
-        for (int ny = std::max(cy - 1, 0); ny <= std::min(cy + 1, g.ncy - 1); ++ny)
-            nb += p->cs_host[(long long)ny * g.ncx + xhi + 1] - p->cs_host[(long long)ny * g.ncx + xlo];
-        if (nb > rbf::kListMaxNb) return RBF_OK;
-        max_nb = std::max(max_nb, (int)nb);
-        for (int t = 0; t < own; t += 64) units.push_back(int2{(int)c, p->cs_host[c] + t});
+    const int* cs = p->cs_host.data();
+    const int ncx = g.ncx, ncy = g.ncy;
+    auto span = [&](int cy, int cxa, int cxb) {
+        const int xlo = std::max(cxa - 1, 0), xhi = std::min(cxb + 1, ncx - 1);
+        long long s = 0;
+        for (int ny = std::max(cy - 1, 0); ny <= std::min(cy + 1, ncy - 1); ++ny)
+            s += cs[(long long)ny * ncx + xhi + 1] - cs[(long long)ny * ncx + xlo];
+        return s;
+    };
+    int cells = rbf::kGroupCells;
+    if (const char* e = std::getenv("RBF_LIST_GROUP_CELLS")) cells = std::atoi(e);
+    cells = std::max(1, std::min(cells, rbf::kGroupCells));
+    const int max_targets = 64 * rbf::kGroupMaxUnits;
+    std::vector<rbf::ListGroup> groups;
+    int nu = 0, max_nb = 0, gmax = 0;
+    auto emit = [&](int cy, int cxa, int cxb, int t0, int t1) {
+        rbf::ListGroup gr{};
+        gr.u0 = nu;
+        gr.nu = (t1 - t0 + 63) / 64;
+        gr.cy = cy;
+        gr.cxa = cxa;
+        gr.cxb = cxb;
+        gr.t0 = t0;
+        gr.t1 = t1;
+        groups.push_back(gr);
+        nu += gr.nu;
+        gmax = std::max(gmax, gr.nu);
+        max_nb = std::max(max_nb, (int)span(cy, cxa, cxb));
+    };
+    for (int cy = 0; cy < ncy; ++cy) {
+        const int* row = cs + (long long)cy * ncx;
+        int cx = 0;
+        while (cx < ncx) {
+            if (row[cx + 1] == row[cx]) {   // no targets: starts no group
+                ++cx;
+                continue;
+            }
+            if (span(cy, cx, cx) > rbf::kListMaxNb) return RBF_OK;
+            int cxb = cx;
+            while (cxb + 1 < ncx && cxb + 2 - cx <= cells && span(cy, cx, cxb + 1) <= rbf::kGroupSpan &&
+                   row[cxb + 2] - row[cx] <= max_targets)
+                ++cxb;
+            if (row[cxb + 1] - row[cx] <= max_targets) {
+                emit(cy, cx, cxb, row[cx], row[cxb + 1]);
+            } else {   // one cell with more targets than a group holds
+                for (int t = row[cx]; t < row[cx + 1]; t += max_targets)
+                    emit(cy, cx, cx, t, std::min(t + max_targets, row[cx + 1]));
+            }
+            cx = cxb + 1;
+        }
     }
-    const int nu = (int)units.size();
     if (nu == 0) return RBF_OK;
-    int2* unit = nullptr;
-    int *len = nullptr, *nbv = nullptr;
+    rbf::ListGroup* group = nullptr;
+    int* len = nullptr;
     long long* off = nullptr;
     unsigned short* idx = nullptr;
-    RBF_TRY(p->alloc_n(&unit, nu));
+    RBF_TRY(p->alloc_n(&group, groups.size()));
     RBF_TRY(p->alloc_n(&len, nu));
-    RBF_TRY(p->alloc_n(&nbv, nu));
     RBF_TRY(p->alloc_n(&off, nu + 1));
-    HIP_TRY(hipMemcpyAsync(unit, units.data(), sizeof(int2) * nu, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(group, groups.data(), sizeof(rbf::ListGroup) * groups.size(),
+                           hipMemcpyHostToDevice, st));
+    rbf::NeighborLists nl{};
+    nl.group = group;
+    nl.off = off;
+    nl.len = len;
+    nl.nunits = nu;
+    nl.ngroups = (int)groups.size();
+    nl.gunits = gmax;
+    nl.max_nb = max_nb;
     const rbf::MatvecArgs a = p->mv_args();
-    HIP_TRY(rbf::launch_list_count(a, unit, nu, len, nbv, st));
+    HIP_TRY(rbf::launch_list_count(a, nl, len, st));
     std::vector<int> hl(nu);
     HIP_TRY(hipMemcpyAsync(hl.data(), len, sizeof(int) * nu, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -439,15 +488,10 @@ rbf_status build_lists(rbf_problem* p, hipStream_t st) {
     for (int u = 0; u < nu; ++u) ho[u + 1] = ho[u] + 64LL * hl[u];
     RBF_TRY(p->alloc_n(&idx, ho[nu]));
     HIP_TRY(hipMemcpyAsync(off, ho.data(), sizeof(long long) * (nu + 1), hipMemcpyHostToDevice, st));
-    HIP_TRY(rbf::launch_list_fill(a, unit, nu, off, len, idx, st));
+    HIP_TRY(rbf::launch_list_fill(a, nl, idx, st));
     HIP_TRY(hipStreamSynchronize(st));
-    p->release(nbv, st);
-    p->nl.unit = unit;
-    p->nl.off = off;
-    p->nl.len = len;
-    p->nl.idx = idx;
-    p->nl.nunits = nu;
-    p->nl.max_nb = max_nb;
+    nl.idx = idx;
+    p->nl = nl;
     return RBF_OK;
 }
 

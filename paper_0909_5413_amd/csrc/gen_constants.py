@@ -27,3 +27,6 @@ print(f"kLn2Hi = {float(head).hex()}")
 print(f"kLn2Lo = {tail.hex()}")
 for k in range(12, 1, -1):
     print(f"1/{k}! = {float(Fraction(1, math.factorial(k))).hex()}")
+# exp2_scaled_t32: Taylor coefficients of exp(f ln2/32) in f, (ln2/32)^i / i!
+for k in range(6, 0, -1):
+    print(f"(ln2/32)^{k}/{k}! = {float((ln2 / 32) ** k / math.factorial(k)).hex()}")

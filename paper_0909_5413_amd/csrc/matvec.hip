@@ -6,14 +6,16 @@
 // of a target lies in the 3x3 block of cells around the target's cell, and in
 // the cell-sorted order each row of three cells is one contiguous range.
 //
-// Mapping: one wavefront per target cell (lanes = the cell's targets, in chunks
-// of 64), cells strided over all waves of a persistent grid.  The sources are
-// wave-uniform, so they stream through the scalar cache into SGPRs (no LDS
-// staging, no broadcast reads); the per-lane work is the distance, the cutoff
-// test and the exponential.  The FP64 exponential reads a table of
-// e^{-n/128} kept in LDS (one copy per workgroup).  Every target sums its
-// sources in a fixed order (rows, then sorted order), so results are
-// bit-reproducible.
+// Two forms.  The candidate kernels (evaluation at arbitrary targets, the
+// neighbour counts, and products whose 3x3 blocks are too large to stage):
+// one wavefront per target cell (lanes = the cell's targets, in chunks of 64),
+// cells strided over all waves of a persistent grid; the sources are
+// wave-uniform, so they stream through the scalar cache into SGPRs, and the
+// cutoff is a per-lane select.  The list kernels (every product of the
+// solver): per-target lists of in-cutoff sources built once at setup, one
+// workgroup per run of cells of one cell row, the run's neighbourhood staged
+// once in LDS and only listed pairs evaluated.  Every target sums its sources
+// in a fixed order (rows, then sorted order), so results are bit-reproducible.
 #include "rbf_device.hpp"
 #include "rbf_internal.hpp"
 
@@ -180,29 +182,28 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec32(Matvec32Args a, const f
 
 // ---- neighbour lists ---------------------------------------------------------
 
-// The three row ranges of cell c's 3x3 block (sorted-order [b, e) per row,
-// empty rows outside the grid) and the first cell column of each range.
+// The three row ranges dy = -1, 0, 1 around cell row cy, each from the column
+// left of cxa to the column right of cxb (clipped to the grid): sorted-order
+// [b, e) per row, empty rows outside the grid, concatenated at base.
 struct Rows {
-    int b[3], e[3], base[3];   // base: local index of the range's first source
-    int n;                     // n_nb
-    int xlo, cx, cy;
+    int b[3], e[3], base[3];   // base: index of the range's first source in the concatenation
+    int n;                     // sources in all three rows
 };
 
-__device__ __forceinline__ Rows block_rows(const int* __restrict__ scell, const Grid& g, int c) {
+__device__ __forceinline__ Rows span_rows(const int* __restrict__ scell, const Grid& g, int cy,
+                                          int cxa, int cxb) {
     Rows r;
     const int ncx = g.ncx, ncy = g.ncy;
-    r.cx = c % ncx;
-    r.cy = c / ncx;
-    r.xlo = r.cx > 0 ? r.cx - 1 : 0;
-    const int xhi = r.cx + 1 < ncx ? r.cx + 1 : ncx - 1;
+    const int xlo = cxa > 0 ? cxa - 1 : 0;
+    const int xhi = cxb + 1 < ncx ? cxb + 1 : ncx - 1;
     int tot = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int ny = r.cy + d - 1;
+        const int ny = cy + d - 1;
         int b = 0, e = 0;
         if (ny >= 0 && ny < ncy) {
-            b = scell[ny * ncx + r.xlo];
-            e = scell[ny * ncx + xhi + 1];
+            b = uniform(scell[ny * ncx + xlo]);
+            e = uniform(scell[ny * ncx + xhi + 1]);
         }
         r.b[d] = b;
         r.e[d] = e;
@@ -213,38 +214,61 @@ __device__ __forceinline__ Rows block_rows(const int* __restrict__ scell, const 
     return r;
 }
 
-// Count (kFill = false) or write (kFill = true) each lane's in-cutoff sources;
-// the decision d2 <= rc2 is the one the candidate kernel takes, bit for bit.
+struct GroupView {
+    int u0, nu, cy, cxa, cxb, t0, t1;
+};
+__device__ __forceinline__ GroupView load_group(const ListGroup* __restrict__ g, int i) {
+    const ListGroup v = g[i];
+    return GroupView{uniform(v.u0), uniform(v.nu), uniform(v.cy), uniform(v.cxa),
+                     uniform(v.cxb), uniform(v.t0), uniform(v.t1)};
+}
+
+// Count (kFill = false) or write (kFill = true) each lane's in-cutoff sources:
+// the group's staged rows are scanned cell by cell in local order, and a lane
+// takes a source only from the three cell columns around its own target's
+// cell and only if d2 <= rc2 -- the decision the candidate kernel takes, bit
+// for bit, over the same 3x3 block.  One wave per unit.
 template <bool kFill>
-__global__ __launch_bounds__(64) void k_list_build(MatvecArgs a, const int2* __restrict__ unit,
-                                                   int* __restrict__ len, int* __restrict__ nb,
-                                                   const long long* __restrict__ off,
-                                                   unsigned short* __restrict__ idx) {
-    const int u = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int2 uc = unit[u];
-    const int c = uniform(uc.x), t0 = uniform(uc.y);
-    const int t1 = uniform(a.scell[c + 1]);
-    const Rows r = block_rows(a.scell, a.g, c);
-    const int t = t0 + lane;
-    const bool act = t < t1;
+__global__ __launch_bounds__(64 * kGroupMaxUnits) void k_list_build(MatvecArgs a, NeighborLists nl,
+                                                                   int* __restrict__ len,
+                                                                   unsigned short* __restrict__ idx) {
+    const GroupView gr = load_group(nl.group, blockIdx.x);
+    const int tid = threadIdx.x, lane = tid & 63, wv = uniform(tid >> 6);
+    if (wv >= gr.nu) return;
+    const int u = gr.u0 + wv;
+    const int ncx = a.g.ncx, ncy = a.g.ncy;
+    const Rows sp = span_rows(a.scell, a.g, gr.cy, gr.cxa, gr.cxb);
+    const int t = gr.t0 + 64 * wv + lane;
+    const bool act = t < gr.t1;
+    int cxt = gr.cxa;   // the target's cell column
+    for (int nx = gr.cxa + 1; nx <= gr.cxb; ++nx)
+        if (t >= a.scell[gr.cy * ncx + nx]) cxt = nx;
     const double xi = act ? a.sx[t] : 0.0, yi = act ? a.sy[t] : 0.0;
+    const int xlo = gr.cxa > 0 ? gr.cxa - 1 : 0;
+    const int xhi = gr.cxb + 1 < ncx ? gr.cxb + 1 : ncx - 1;
     int cnt = 0;
-    unsigned short* mine = kFill ? idx + off[u] + 4 * lane : nullptr;
+    unsigned short* mine = kFill ? idx + nl.off[u] + 4 * lane : nullptr;
     for (int d = 0; d < 3; ++d) {
-        const int b = uniform(r.b[d]), e = uniform(r.e[d]), base = uniform(r.base[d]);
-        for (int s = b; s < e; ++s) {
-            const double dx = xi - a.sx[s], dy = yi - a.sy[s];
-            const bool in = act && __builtin_fma(dx, dx, dy * dy) <= a.rc2;
-            if (in) {
-                if (kFill) mine[256 * (cnt >> 2) + (cnt & 3)] = (unsigned short)(base + s - b);
-                ++cnt;
+        const int ny = gr.cy + d - 1;
+        if (ny < 0 || ny >= ncy) continue;
+        const int shift = sp.base[d] - sp.b[d];
+        for (int nx = xlo; nx <= xhi; ++nx) {
+            const bool near = act && nx >= cxt - 1 && nx <= cxt + 1;
+            if (!__any(near)) continue;
+            const int b = uniform(a.scell[ny * ncx + nx]), e = uniform(a.scell[ny * ncx + nx + 1]);
+            for (int s = b; s < e; ++s) {
+                const double dx = xi - a.sx[s], dy = yi - a.sy[s];
+                const bool in = near && __builtin_fma(dx, dx, dy * dy) <= a.rc2;
+                if (in) {
+                    if (kFill) mine[256 * (cnt >> 2) + (cnt & 3)] = (unsigned short)(16 * (s + shift));
+                    ++cnt;
+                }
             }
         }
     }
     if (kFill) {
         const int L = len[u];
-        for (int k = cnt; k < L; ++k) mine[256 * (k >> 2) + (k & 3)] = (unsigned short)r.n;
+        for (int k = cnt; k < L; ++k) mine[256 * (k >> 2) + (k & 3)] = (unsigned short)(16 * sp.n);
     } else {
         int m = cnt;
 #pragma unroll
@@ -252,63 +276,76 @@ __global__ __launch_bounds__(64) void k_list_build(MatvecArgs a, const int2* __r
             const int v = __shfl_xor(m, o, 64);
             m = v > m ? v : m;
         }
-        if (lane == 0) {
-            len[u] = (m + 3) & ~3;
-            nb[u] = r.n;
-        }
+        if (lane == 0) len[u] = (m + 3) & ~3;
     }
 }
 
-// y[t] = norm * sum over the target's list of w[s] exp(mk d2): the unit's
-// sources staged in LDS as 32-byte records (x, y, w), the null source at the
-// cell centre with weight 0, the exponential from a 32-entry table (also in
-// LDS); four list entries per 8-byte load, loaded two loop passes ahead.
-__global__ __launch_bounds__(64) void k_matvec64_lists(MatvecArgs a, NeighborLists nl,
-                                                       const double* __restrict__ w,
-                                                       double* __restrict__ y) {
-    extern __shared__ double smem[];
-    const int u = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int2 uc = nl.unit[u];
-    const int c = uniform(uc.x), t0 = uniform(uc.y);
-    const int t1 = uniform(a.scell[c + 1]);
-    const Rows r = block_rows(a.scell, a.g, c);
+// LDS layout of the FP64 list matvec (a static allocation, so every address
+// offset is a compile-time constant): the staged weights W[q] at byte 8 q, the
+// coordinates (x, y)[q] at byte kXYBase + 16 q, so a list entry e = 16 q
+// addresses both (e / 2 and e + kXYBase; consecutive sources fall on distinct
+// banks in both arrays), then the 32-entry exponential table.
+constexpr int kXYBase = 8 * (kGroupSpan + 1);
+// FP32 form: (x, y)[q] as float2 at byte 8 q (e / 2), w[q] at kW32Base + 4 q (e / 4).
+constexpr int kW32Base = 8 * (kGroupSpan + 1);
+
+// y[t] = norm * sum over the target's list of w[s] 2^(beta d2 / 32).  One
+// workgroup per group, one wave per unit; the null source (weight 0) sits at
+// the middle of the group; four list entries per 8-byte load, loaded two loop
+// passes ahead.
+__global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec64_lists(MatvecArgs a,
+                                                                       NeighborLists nl,
+                                                                       const double* __restrict__ w,
+                                                                       double* __restrict__ y) {
+    __shared__ __attribute__((aligned(16))) char lds[kXYBase + 16 * (kGroupSpan + 1) + 256];
+    const GroupView gr = load_group(nl.group, blockIdx.x);
+    const int tid = threadIdx.x, lane = tid & 63, wv = uniform(tid >> 6);
+    const Rows r = span_rows(a.scell, a.g, gr.cy, gr.cxa, gr.cxb);
     const int n = r.n;
-    double* T32 = smem;                 // 32 entries
-    double4* S = reinterpret_cast<double4*>(smem + 32);
-    if (lane < 32) T32[lane] = a.t32[lane];
+    double* W = reinterpret_cast<double*>(lds);
+    double2* XY = reinterpret_cast<double2*>(lds + kXYBase);
+    double* T32 = reinterpret_cast<double*>(lds + kXYBase + 16 * (kGroupSpan + 1));
+    if (tid < 32) T32[tid] = a.t32[tid];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int b = r.b[d], cnt = r.e[d] - r.b[d], base = r.base[d];
-        for (int q = lane; q < cnt; q += 64)
-            S[base + q] = double4{a.sx[b + q], a.sy[b + q], w[b + q], 0.0};
+        for (int q = tid; q < cnt; q += blockDim.x) {
+            XY[base + q] = double2{a.sx[b + q], a.sy[b + q]};
+            W[base + q] = w[b + q];
+        }
     }
-    const double xc = a.g.x0 + (r.cx + 0.5) * a.g.L, yc = a.g.y0 + (r.cy + 0.5) * a.g.L;
-    if (lane == 0) S[n] = double4{xc, yc, 0.0, 0.0};
-    const int t = t0 + lane;
-    const bool act = t < t1;
-    const double xi = act ? a.sx[t] : xc;
-    const double yi = act ? a.sy[t] : yc;
+    const double xm = a.g.x0 + (0.5 * (gr.cxa + gr.cxb) + 0.5) * a.g.L;
+    const double ym = a.g.y0 + (gr.cy + 0.5) * a.g.L;
+    if (tid == 0) {
+        XY[n] = double2{xm, ym};
+        W[n] = 0.0;
+    }
+    __syncthreads();
+    if (wv >= gr.nu) return;
+    const int u = gr.u0 + wv;
+    const int t = gr.t0 + 64 * wv + lane;
+    const bool act = t < gr.t1;
+    const double xi = act ? a.sx[t] : xm;
+    const double yi = act ? a.sy[t] : ym;
     const int L = uniform(nl.len[u]);   // multiple of 4, >= 4
     const uint2* lp = reinterpret_cast<const uint2*>(nl.idx + nl.off[u]) + lane;
     // two list registers in turn, each reloaded two passes ahead (no copies)
     uint2 qa = lp[0];
     uint2 qb = L > 4 ? lp[64] : uint2{0u, 0u};
-    __syncthreads();
+    const double beta = a.beta;
     double acc0 = 0.0, acc1 = 0.0;
+    auto pair = [&](unsigned exy, unsigned ew, double& acc) {
+        const double2 s = *reinterpret_cast<const double2*>(lds + kXYBase + exy);
+        const double ws = *reinterpret_cast<const double*>(lds + ew);
+        const double dx = xi - s.x, dy = yi - s.y;
+        const double e = exp2_scaled_t32(__builtin_fma(dx, dx, dy * dy), beta, T32);
+        acc = __builtin_fma(ws, e, acc);
+    };
     auto four = [&](const uint2 q4) {
-        const int q[4] = {(int)(q4.x & 0xffff), (int)(q4.x >> 16), (int)(q4.y & 0xffff),
-                          (int)(q4.y >> 16)};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double4 s = S[q[j]];
-            const double dx = xi - s.x, dy = yi - s.y;
-            const double e = exp_neg_t32(__builtin_fma(dx, dx, dy * dy) * a.mk, T32);
-            if (j & 1)
-                acc1 = __builtin_fma(s.z, e, acc1);
-            else
-                acc0 = __builtin_fma(s.z, e, acc0);
-        }
+        pair(q4.x & 0xffffu, (q4.x >> 1) & 0x7fffu, acc0);
+        pair(q4.x >> 16, q4.x >> 17, acc1);
+        pair(q4.y & 0xffffu, (q4.y >> 1) & 0x7fffu, acc0);
+        pair(q4.y >> 16, q4.y >> 17, acc1);
     };
     for (int k = 0; k < L; k += 8) {
         four(qa);
@@ -321,59 +358,69 @@ __global__ __launch_bounds__(64) void k_matvec64_lists(MatvecArgs a, NeighborLis
     if (act) y[t] = (acc0 + acc1) * a.norm;
 }
 
-// FP32 form: the staged sources are moved into the target cell's frame (the
-// scaled cell-relative coordinates plus the cell offset), so d2 is the negated
-// base-2 exponent; Kahan-compensated FP32 accumulation, FP64 output.
-__global__ __launch_bounds__(64) void k_matvec32_lists(Matvec32Args a, NeighborLists nl,
-                                                       const double* __restrict__ w,
-                                                       double* __restrict__ y) {
-    extern __shared__ double smem[];
-    const int u = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int2 uc = nl.unit[u];
-    const int c = uniform(uc.x), t0 = uniform(uc.y);
-    const int t1 = uniform(a.scell[c + 1]);
-    const Rows r = block_rows(a.scell, a.g, c);
+// FP32 form: the group's sources are staged in one frame centred on the group
+// (scaled coordinates: the cell-centre-relative FP32 ones plus the cell offset,
+// summed in FP64 and rounded once), so d2 is the negated base-2 exponent;
+// Kahan-compensated FP32 accumulation, FP64 output.
+__global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec32_lists(Matvec32Args a,
+                                                                       NeighborLists nl,
+                                                                       const double* __restrict__ w,
+                                                                       double* __restrict__ y) {
+    __shared__ __attribute__((aligned(16))) char lds[kW32Base + 4 * (kGroupSpan + 1)];
+    const GroupView gr = load_group(nl.group, blockIdx.x);
+    const int tid = threadIdx.x, lane = tid & 63, wv = uniform(tid >> 6);
+    const Rows r = span_rows(a.scell, a.g, gr.cy, gr.cxa, gr.cxb);
     const int n = r.n;
-    float2* XY = reinterpret_cast<float2*>(smem);
-    float* W = reinterpret_cast<float*>(smem) + 2 * (nl.max_nb + 1);
+    float2* XY = reinterpret_cast<float2*>(lds);
+    float* W = reinterpret_cast<float*>(lds + kW32Base);
     const int ncx = a.g.ncx;
+    const double mid = 0.5 * (gr.cxa + gr.cxb);
+    const double Ls = (double)a.Ls;
+    const int xlo = gr.cxa > 0 ? gr.cxa - 1 : 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int ny = r.cy + d - 1;
+        const int ny = gr.cy + d - 1;
         const int b = r.b[d], cnt = r.e[d] - r.b[d], base = r.base[d];
-        for (int q = lane; q < cnt; q += 64) {
+        for (int q = tid; q < cnt; q += blockDim.x) {
             const int s = b + q;
             // cell column of s within the row range
-            int nx = r.xlo;
+            int nx = xlo;
             while (nx + 1 < ncx && a.scell[ny * ncx + nx + 1] <= s) ++nx;
-            XY[base + q] = float2{a.sx[s] + (float)(nx - r.cx) * a.Ls,
-                                  a.sy[s] + (float)(d - 1) * a.Ls};
+            XY[base + q] = float2{(float)((double)a.sx[s] + (nx - mid) * Ls),
+                                  (float)((double)a.sy[s] + (double)(d - 1) * Ls)};
             W[base + q] = (float)w[s];
         }
     }
-    if (lane == 0) {
+    if (tid == 0) {
         XY[n] = float2{0.f, 0.f};
         W[n] = 0.f;
     }
-    const int t = t0 + lane;
-    const bool act = t < t1;
-    const float xi = act ? a.sx[t] : 0.f, yi = act ? a.sy[t] : 0.f;
     __syncthreads();
+    if (wv >= gr.nu) return;
+    const int u = gr.u0 + wv;
+    const int t = gr.t0 + 64 * wv + lane;
+    const bool act = t < gr.t1;
+    int cxt = gr.cxa;   // the target's cell column
+    for (int nx = gr.cxa + 1; nx <= gr.cxb; ++nx)
+        if (t >= a.scell[gr.cy * ncx + nx]) cxt = nx;
+    const float xi = act ? (float)((double)a.sx[t] + (cxt - mid) * Ls) : 0.f;
+    const float yi = act ? a.sy[t] : 0.f;
     const int L = uniform(nl.len[u]);   // multiple of 4, >= 4
     const uint2* lp = reinterpret_cast<const uint2*>(nl.idx + nl.off[u]) + lane;
     uint2 qa = lp[0];
     uint2 qb = L > 4 ? lp[64] : uint2{0u, 0u};
     Kahan32 acc;
+    auto pair = [&](unsigned exy, unsigned ew) {
+        const float2 s = *reinterpret_cast<const float2*>(lds + exy);
+        const float ws = *reinterpret_cast<const float*>(lds + kW32Base + ew);
+        const float dx = xi - s.x, dy = yi - s.y;
+        acc.add(ws * exp2_f32(-__builtin_fmaf(dx, dx, dy * dy)));
+    };
     auto four = [&](const uint2 q4) {
-        const int q[4] = {(int)(q4.x & 0xffff), (int)(q4.x >> 16), (int)(q4.y & 0xffff),
-                          (int)(q4.y >> 16)};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float2 s = XY[q[j]];
-            const float dx = xi - s.x, dy = yi - s.y;
-            acc.add(W[q[j]] * exp2_f32(-__builtin_fmaf(dx, dx, dy * dy)));
-        }
+        pair((q4.x >> 1) & 0x7fffu, (q4.x >> 2) & 0x3fffu);
+        pair(q4.x >> 17, q4.x >> 18);
+        pair((q4.y >> 1) & 0x7fffu, (q4.y >> 2) & 0x3fffu);
+        pair(q4.y >> 17, q4.y >> 18);
     };
     for (int k = 0; k < L; k += 8) {
         four(qa);
@@ -425,33 +472,30 @@ hipError_t launch_matvec32(const Matvec32Args& a, const double* w, float* w32, d
     return hipGetLastError();
 }
 
-hipError_t launch_list_count(const MatvecArgs& a, const int2* unit, int nunits, int* len, int* nb,
+hipError_t launch_list_count(const MatvecArgs& a, const NeighborLists& nl, int* len,
                              hipStream_t st) {
-    if (nunits > 0)
-        k_list_build<false><<<nunits, 64, 0, st>>>(a, unit, len, nb, nullptr, nullptr);
+    if (nl.ngroups > 0)
+        k_list_build<false><<<nl.ngroups, 64 * nl.gunits, 0, st>>>(a, nl, len, nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_list_fill(const MatvecArgs& a, const int2* unit, int nunits,
-                            const long long* off, const int* len, unsigned short* idx,
+hipError_t launch_list_fill(const MatvecArgs& a, const NeighborLists& nl, unsigned short* idx,
                             hipStream_t st) {
-    if (nunits > 0)
-        k_list_build<true><<<nunits, 64, 0, st>>>(a, unit, const_cast<int*>(len), nullptr, off,
-                                                  idx);
+    if (nl.ngroups > 0)
+        k_list_build<true><<<nl.ngroups, 64 * nl.gunits, 0, st>>>(a, nl, const_cast<int*>(nl.len),
+                                                                   idx);
     return hipGetLastError();
 }
 
 hipError_t launch_matvec64_lists(const MatvecArgs& a, const NeighborLists& nl, const double* w,
                                  double* y, hipStream_t st) {
-    const size_t lds = sizeof(double) * (32 + 4 * (size_t)(nl.max_nb + 1));
-    if (nl.nunits > 0) k_matvec64_lists<<<nl.nunits, 64, lds, st>>>(a, nl, w, y);
+    if (nl.ngroups > 0) k_matvec64_lists<<<nl.ngroups, 64 * nl.gunits, 0, st>>>(a, nl, w, y);
     return hipGetLastError();
 }
 
 hipError_t launch_matvec32_lists(const Matvec32Args& a, const NeighborLists& nl, const double* w,
                                  double* y, hipStream_t st) {
-    const size_t lds = sizeof(float) * 3 * (size_t)(nl.max_nb + 1);
-    if (nl.nunits > 0) k_matvec32_lists<<<nl.nunits, 64, lds, st>>>(a, nl, w, y);
+    if (nl.ngroups > 0) k_matvec32_lists<<<nl.ngroups, 64 * nl.gunits, 0, st>>>(a, nl, w, y);
     return hipGetLastError();
 }
 

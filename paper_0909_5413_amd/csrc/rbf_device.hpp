@@ -95,6 +95,33 @@ __device__ __forceinline__ double exp_neg_t32(double x, const double* T) {
     return __builtin_amdgcn_ldexp(T[k & 31] * p, k >> 5);
 }
 
+// ---------------------------------------------------------------------------
+// 2^(y/32) for y = d2 * beta <= 0, where beta folds the Gaussian's -1/(2 sigma^2)
+// and 32/ln2 (so 2^(y/32) = exp(-d2 / (2 sigma^2))), from a 32-entry table
+// T[j] = 2^(j/32) (correctly rounded, in LDS, as for exp_neg_t32).
+// k = rint(y) = 32 n + j is read from the fused product against the 1.5*2^52
+// shift; f = y - k comes from a second fused multiply-add of the same exact
+// product (one rounding, |f| <= 1/2), so no split constant is needed: the
+// reduction's only error is beta's own rounding.  2^(f/32) = exp(f ln2/32) is
+// the degree-6 Taylor polynomial in f with coefficients (ln2/32)^i / i!
+// (truncation below (ln2/64)^7/7! < 3.5e-18).  Valid for -700*32/ln2 < y <= 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp2_scaled_t32(double d2, double beta, const double* T) {
+    const double kShift = 0x1.8p52;
+    const double t = __builtin_fma(d2, beta, kShift);
+    const double kf = t - kShift;
+    const int k = (int)__double2loint(t);
+    const double f = __builtin_fma(d2, beta, -kf);
+    double p = 0x1.430912f86c787p-43;                 // (ln2/32)^6/6!
+    p = __builtin_fma(p, f, 0x1.5d87fe78a6731p-35);    // (ln2/32)^5/5!
+    p = __builtin_fma(p, f, 0x1.3b2ab6fba4e77p-27);    // (ln2/32)^4/4!
+    p = __builtin_fma(p, f, 0x1.c6b08d704a0c0p-20);    // (ln2/32)^3/3!
+    p = __builtin_fma(p, f, 0x1.ebfbdff82c58fp-13);    // (ln2/32)^2/2!
+    p = __builtin_fma(p, f, 0x1.62e42fefa39efp-6);     // (ln2/32)^1/1!
+    p = __builtin_fma(p, f, 1.0);
+    return __builtin_amdgcn_ldexp(T[k & 31] * p, k >> 5);
+}
+
 // 2^x in FP32 on the hardware transcendental unit (v_exp_f32).
 __device__ __forceinline__ float exp2_f32(float x) { return __builtin_amdgcn_exp2f(x); }
 

@@ -64,6 +64,7 @@ struct MatvecArgs {
     Grid g;
     double rc2;             // cutoff^2
     double mk;              // -1 / (2 sigma^2)
+    double beta;            // -32 / (2 sigma^2 ln2): exp(mk d2) = 2^(beta d2 / 32)
     double norm;            // 1 / (2 pi sigma^2)
     const double* etab;     // e^{-n/128}, n < ntab, or NULL (no table)
     int ntab;
@@ -91,31 +92,45 @@ hipError_t launch_matvec32(const Matvec32Args& a, const double* w, float* w32, d
                            long long n, hipStream_t st);
 
 // ---- neighbour lists (matvec.hip) --------------------------------------------
-// A unit is up to 64 targets of one cell (one per lane) together with the
-// sources of the 3x3 block of cells around it, indexed locally: the row ranges
-// dy = -1, 0, 1 in that order, each the contiguous sorted range of up to three
-// cells, concatenated (n_nb sources).  A unit's list holds, per lane, the local
-// indices of the target's in-cutoff sources in local order, padded to the
-// unit's longest list (a multiple of 4) with the index n_nb of a null source;
-// entry k of lane l sits at off[u] + 256 (k / 4) + 4 l + k % 4, so one 8-byte
-// load fetches four indices.
+// A group is a run of consecutive cells cxa..cxb of one cell row cy together
+// with a range [t0, t1) of their targets (all of them unless one cell alone is
+// split over several groups); one workgroup serves it.  The group stages once
+// the sources of the rows dy = -1, 0, 1 around its cells, each row the
+// contiguous sorted range from the column left of cxa to the column right of
+// cxb, concatenated in that order (n_span sources).  Its targets are cut into
+// units of 64 consecutive targets, one per wave (lane = target).  A unit's
+// list holds, per lane, the target's in-cutoff sources (those of its own 3x3
+// block with d2 <= rc2) in local order (rows, then sorted order) as 16 * their
+// index in the staging, padded to the unit's longest list (a multiple of 4)
+// with 16 * n_span, a null source; entry k of lane l sits at
+// off[u] + 256 (k / 4) + 4 l + k % 4, so one 8-byte load fetches four entries.
+struct ListGroup {
+    int u0, nu;                // first unit, units
+    int cy, cxa, cxb;          // cell row and columns
+    int t0, t1;                // targets (sorted order)
+    int pad;
+};
 struct NeighborLists {
-    const int2* unit;          // (cell, first target) per unit
+    const ListGroup* group;
     const long long* off;      // per unit, entries
     const int* len;            // per unit, padded list length
     const unsigned short* idx;
-    int nunits;
-    int max_nb;                // largest n_nb over the units
+    int nunits, ngroups;
+    int gunits;                // most units in one group (waves per workgroup)
+    int max_nb;                // largest n_span over the groups
 };
-// Sources per neighbourhood that a list-driven launch can stage in LDS
-// (32-byte records).
+// Sources one 3x3 block may hold for the lists to be built (16-bit entries of
+// 16 * index, LDS), the staged sources and cell columns a group grows to, and
+// the units (waves) of one group.
 constexpr int kListMaxNb = 2047;
+constexpr int kGroupSpan = 2047;
+constexpr int kGroupCells = 8;
+constexpr int kGroupMaxUnits = 8;
 // len[u] = the unit's padded list length (max in-cutoff count over its lanes,
-// rounded up to 4); nb[u] = its n_nb.
-hipError_t launch_list_count(const MatvecArgs& a, const int2* unit, int nunits, int* len,
-                             int* nb, hipStream_t st);
-hipError_t launch_list_fill(const MatvecArgs& a, const int2* unit, int nunits,
-                            const long long* off, const int* len, unsigned short* idx,
+// rounded up to 4); nb[u] = its group's n_span.
+hipError_t launch_list_count(const MatvecArgs& a, const NeighborLists& nl, int* len,
+                             hipStream_t st);
+hipError_t launch_list_fill(const MatvecArgs& a, const NeighborLists& nl, unsigned short* idx,
                             hipStream_t st);
 // The same products as launch_matvec64 / launch_matvec32 (targets = sources),
 // driven by the lists: every evaluated pair is an interaction.

@@ -136,3 +136,48 @@ def test_device_exp_table_constants_accurate():
         ref = math.exp(float(x))
         worst = max(worst, abs(got - ref) / ref)
     assert worst < 5e-16, worst
+
+
+def _device_exp2_scaled(d2, beta):
+    """exp2_scaled_t32 step by step: the fused products d2*beta are exact
+    before their one rounding, the table entries 2^(j/32) correctly rounded."""
+    src = open(os.path.join(ROOT, "paper_0909_5413_amd", "csrc", "rbf_device.hpp")).read()
+    body = src[src.index("double exp2_scaled_t32"):]
+    body = body[:body.index("return __builtin_amdgcn_ldexp")]
+    shift = float.fromhex(re.search(r"const double kShift = ([0-9a-fx.p+-]+);", body).group(1))
+    first = float.fromhex(re.search(r"double p = ([0-9a-fx.p+-]+);", body).group(1))
+    coefs = [float.fromhex(h) for h in re.findall(r"(0x[0-9a-f.]+p[+-]?\d+)\);\s*// \(ln2", body)]
+    assert len(coefs) == 5
+    t = _fma(d2, beta, shift)
+    kf = t - shift
+    k = int(kf)
+    f = _fma(d2, beta, -kf)
+    assert abs(f) <= 0.5
+    p = first
+    for c in coefs + [1.0]:
+        p = _fma(p, f, c)
+    j, n = k & 31, k >> 5
+    return math.ldexp(_exp2_frac(j) * p, n)
+
+
+def test_device_exp2_scaled_constants_accurate():
+    """The list matvec's exponential, 2^(d2 beta / 32) with the reduction read
+    from two fused products: within a few units of the last place of the exact
+    2^(d2 beta / 32) (beta taken as exact), over the cutoff's range and beyond,
+    including the tie points y = k + 1/2."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    rng = np.random.default_rng(5)
+    sigma = 0.0025
+    beta = -16.0 / (sigma * sigma * math.log(2.0))
+    d2max = 36.0 * sigma * sigma
+    d2s = list(rng.uniform(0.0, d2max, 400)) + list(rng.uniform(d2max, 30 * d2max, 50))
+    d2s += [0.0, d2max, (0.5 / -beta), (31.5 / -beta)]
+    worst = 0.0
+    for d2 in d2s:
+        got = _device_exp2_scaled(float(d2), beta)
+        y = Decimal(Fraction(float(d2)).numerator) / Decimal(Fraction(float(d2)).denominator)
+        y = y * Decimal(Fraction(beta).numerator) / Decimal(Fraction(beta).denominator)
+        ref = float(Decimal(2) ** (y / 32))
+        worst = max(worst, abs(got - ref) / ref)
+    assert worst < 4e-16, worst
