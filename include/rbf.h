@@ -218,6 +218,17 @@ typedef enum {
  * (RBF_K_SETUP_KINDS entries each, caller-owned host arrays).
  * Errors: RBF_EINVAL (NULL argument), RBF_ESTATE (no profiled setup yet). */
 rbf_status rbf_set_profiling(rbf_problem* p, int enable);
+
+/* Graph launches of the Arnoldi step (Section 2.2's GMRES iteration; the
+ * Gram-Schmidt work of step j -- two classical passes, the norm, the
+ * normalisation and the read-back of the Hessenberg column -- captured once per
+ * j as a HIP graph -- when step j comes round a second time on the handle --
+ * and replayed on the solve's stream).  enable != 0 uses them; enable == 0
+ * (the default: on ROCm 7 one graph launch of these few kernels costs more
+ * than launching them back to back) launches the same kernels one by one.
+ * The results are bit-identical either way.  A handle whose capture fails
+ * falls back to single launches by itself.  Errors: RBF_EINVAL (NULL handle). */
+rbf_status rbf_set_graphs(rbf_problem* p, int enable);
 rbf_status rbf_setup_kernel_times(const rbf_problem* p, rbf_precision precision, double* ms,
                                   int* launches);
 

@@ -28,7 +28,7 @@ EXPORTED = [
     "rbf_precond_setup", "rbf_solve", "rbf_solve_device", "rbf_evaluate",
     "rbf_evaluate_device", "rbf_destroy", "rbf_block_cache", "rbf_grid", "rbf_binning",
     "rbf_neighbor_counts", "rbf_matvec_device", "rbf_precond_apply_device",
-    "rbf_precond_block", "rbf_set_profiling", "rbf_setup_kernel_times",
+    "rbf_precond_block", "rbf_set_profiling", "rbf_set_graphs", "rbf_setup_kernel_times",
     "rbf_server_default_opts", "rbf_server_create", "rbf_server_submit", "rbf_server_wait",
     "rbf_server_stats", "rbf_server_destroy", "rbf_status_string", "rbf_last_error",
 ]
@@ -114,6 +114,7 @@ def lib():
         "rbf_precond_apply_device": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
         "rbf_precond_block": (C.c_int, [vp, C.c_longlong, C.c_int, vp, vp, ip, ip]),
         "rbf_set_profiling": (C.c_int, [vp, C.c_int]),
+        "rbf_set_graphs": (C.c_int, [vp, C.c_int]),
         "rbf_server_default_opts": (None, [C.POINTER(ServerOpts)]),
         "rbf_server_create": (C.c_int, [C.POINTER(ServerOpts), pp]),
         "rbf_server_submit": (C.c_int, [vp, vp, vp, C.c_longlong, C.c_double, C.c_double, C.c_int,
@@ -291,6 +292,10 @@ def rbf_precond_apply_device(h: int, d_v, d_z, precision: int = RBF_FP64,
 
 def rbf_set_profiling(h: int, enable: bool = True):
     _check(lib().rbf_set_profiling(h, 1 if enable else 0), "rbf_set_profiling")
+
+
+def rbf_set_graphs(h: int, enable: bool = True):
+    _check(lib().rbf_set_graphs(h, 1 if enable else 0), "rbf_set_graphs")
 
 
 def rbf_setup_kernel_times(h: int, precision: int = RBF_FP64) -> dict:

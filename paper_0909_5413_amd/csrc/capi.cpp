@@ -263,6 +263,17 @@ struct rbf_problem {
     bool solved = false;
     rbf::NeighborLists nl{};           // matvec neighbour lists (nunits == 0: none)
     bool profiling = false;            // event timing of the setup launches
+    // Arnoldi step: the Gram-Schmidt part of step j (two classical passes, the
+    // norm, the normalisation and the read-back of the H column into pinned
+    // host memory) as one captured graph per j, built on first use and kept
+    // while the workspace stands; events time the step's phases.
+    hipStream_t gstream = nullptr;     // capture stream (default priority)
+    std::vector<hipGraphExec_t> gs_exec;
+    std::vector<int> gs_uses;          // launches of step j's work so far
+    bool use_graphs = false;           // rbf_set_graphs
+    bool graphs_off = false;           // capture failed once: launch eagerly
+    double* hh = nullptr;              // pinned host, 3 * 64 + 1 doubles
+    hipEvent_t pev[4] = {};
     bool ktimes_valid[2] = {false, false};
     double kms[2][RBF_K_SETUP_KINDS] = {};
     int kcount[2][RBF_K_SETUP_KINDS] = {};
@@ -310,11 +321,22 @@ struct rbf_problem {
         if (hipEventRecord(done, st) != hipSuccess) (void)hipStreamSynchronize(st);
     }
     mutable hipEvent_t done = nullptr;
+    void drop_graphs() {
+        for (hipGraphExec_t& e : gs_exec)
+            if (e) (void)hipGraphExecDestroy(e);
+        gs_exec.clear();
+        gs_uses.clear();
+    }
     ~rbf_problem() {
         if (done) {
             (void)hipEventSynchronize(done);
             (void)hipEventDestroy(done);
         }
+        drop_graphs();
+        if (gstream) (void)hipStreamDestroy(gstream);
+        if (hh) (void)hipHostFree(hh);
+        for (hipEvent_t& e : pev)
+            if (e) (void)hipEventDestroy(e);
         for (auto& b : bufs) BlockCache::get().put(device, b.p, b.bytes, nullptr, false);
     }
 
@@ -811,7 +833,16 @@ rbf_status rasm(rbf_problem* p, rbf_precision prec, const double* v, double* z, 
 }
 
 rbf_status ensure_workspace(rbf_problem* p, int m, hipStream_t st) {
+    if (!p->hh) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&p->hh), sizeof(double) * (3 * 64 + 1)) !=
+            hipSuccess) {
+            p->hh = nullptr;
+            return fail(RBF_ENOMEM, "pinned host buffer of the Arnoldi step");
+        }
+        for (hipEvent_t& e : p->pev) HIP_TRY(hipEventCreate(&e));
+    }
     if (p->ws_m >= m) return RBF_OK;
+    p->drop_graphs();   // they refer to the old basis
     if (p->V) {
         p->release(p->V, st);
         p->V = nullptr;
@@ -857,26 +888,92 @@ struct CycleResult {
     bool breakdown = false;
 };
 
+// Step j of the Arnoldi process after the product w = A M^-1 v_j: classical
+// Gram-Schmidt applied twice (h1, h2), ||w||^2, v_{j+1} = w / ||w||, and the
+// device H column (h1, h2, ||w||^2) copied into p->hh.
+hipError_t enqueue_gram_schmidt(rbf_problem* p, int j, hipStream_t st) {
+    const long long n = p->n;
+    double* V = p->V;
+    double* h1 = p->hdev;
+    double* h2 = p->hdev + 64;
+    double* hn2 = p->hdev + 128;
+    hipError_t e;
+    if ((e = rbf::launch_multidot(V, n, j + 1, p->w, n, p->partial, h1, st)) != hipSuccess) return e;
+    if ((e = rbf::launch_multi_axpy(V, n, j + 1, h1, p->w, n, -1.0, st)) != hipSuccess) return e;
+    if ((e = rbf::launch_multidot(V, n, j + 1, p->w, n, p->partial, h2, st)) != hipSuccess) return e;
+    if ((e = rbf::launch_multi_axpy(V, n, j + 1, h2, p->w, n, -1.0, st)) != hipSuccess) return e;
+    if ((e = rbf::launch_multidot(p->w, 0, 1, p->w, n, p->partial, hn2, st)) != hipSuccess) return e;
+    if ((e = rbf::launch_scale_by_inv(p->w, hn2, V + (long long)(j + 1) * n, n, st)) != hipSuccess)
+        return e;
+    return hipMemcpyAsync(p->hh, p->hdev, sizeof(double) * (2 * 64 + 1), hipMemcpyDeviceToHost, st);
+}
+
+// The same work as one graph launch, captured on the problem's own stream when
+// step j comes round the second time (a restart, the next outer step of the
+// mixed form, the next solve on the handle), so that a capture is only paid
+// for where it is replayed; falls back to single launches if capture fails.
+rbf_status gram_schmidt(rbf_problem* p, int j, hipStream_t st) {
+    if ((int)p->gs_exec.size() <= j) {
+        p->gs_exec.resize(j + 1, nullptr);
+        p->gs_uses.resize(j + 1, 0);
+    }
+    if (p->use_graphs && !p->graphs_off && p->gs_uses[j]++ > 0) {
+        if (!p->gs_exec[j]) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            bool ok = p->gstream || hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) == hipSuccess;
+            if (ok) ok = hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                const hipError_t le = enqueue_gram_schmidt(p, j, p->gstream);
+                const hipError_t ce = hipStreamEndCapture(p->gstream, &graph);
+                ok = le == hipSuccess && ce == hipSuccess && graph != nullptr;
+            }
+            if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            if (ok) {
+                p->gs_exec[j] = exec;
+            } else {
+                if (exec) (void)hipGraphExecDestroy(exec);
+                p->graphs_off = true;
+            }
+        }
+        if (!p->graphs_off) {
+            HIP_TRY(hipGraphLaunch(p->gs_exec[j], st));
+            return RBF_OK;
+        }
+    }
+    HIP_TRY(enqueue_gram_schmidt(p, j, st));
+    return RBF_OK;
+}
+
+float event_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    return hipEventElapsedTime(&ms, a, b) == hipSuccess ? ms : 0.f;
+}
+
 rbf_status gmres_cycles(rbf_problem* p, rbf_precision prec, const double* b, double* x, int m,
                         double tol_abs, int max_cycles, int iter_budget, hipStream_t st,
                         CycleResult* res, PhaseTimes* pt, const double* r0) {
     const long long n = p->n;
     double* V = p->V;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
-    double hh[3 * 64 + 1];
     for (int cyc = 0; cyc < max_cycles && res->iters < iter_budget; ++cyc) {
-        Timer t_res;
         // r = b - A x  into V_0
+        bool timed = false;
         if (r0 && cyc == 0) {   // residual of the starting x already known
             HIP_TRY(hipMemcpyAsync(V, r0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         } else {
+            HIP_TRY(hipEventRecord(p->pev[0], st));
             RBF_TRY(matvec(p, prec, x, p->w, st));
+            HIP_TRY(hipEventRecord(p->pev[1], st));
+            timed = true;
             HIP_TRY(rbf::launch_sub(b, p->w, V, n, st));
             (prec == RBF_FP64 ? pt->mv64 : pt->mv32) += 1;
         }
         double beta2;
-        RBF_TRY(norm2(p, V, &beta2, st));
-        pt->matmult += t_res.sec();
+        RBF_TRY(norm2(p, V, &beta2, st));   // waits for the stream
+        if (timed) pt->matmult += 1e-3 * event_ms(p->pev[0], p->pev[1]);
         double beta = std::sqrt(beta2);
         if (!std::isfinite(beta)) return fail(RBF_ENAN, "non-finite residual");
         res->est = beta;
@@ -889,33 +986,22 @@ rbf_status gmres_cycles(rbf_problem* p, rbf_precision prec, const double* b, dou
         bool stop = false;
         for (int j = 0; j < m && !stop; ++j) {
             double* vj = V + (long long)j * n;
-            Timer t1;
+            // the step's launches are enqueued back to back; the one wait is
+            // for the H column, and events time the phases
+            HIP_TRY(hipEventRecord(p->pev[0], st));
             RBF_TRY(rasm(p, prec, vj, p->z, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            double t_ms = t1.sec();
+            HIP_TRY(hipEventRecord(p->pev[1], st));
             pt->pc += 1;
-            Timer t2;
             RBF_TRY(matvec(p, prec, p->z, p->w, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            double t_mm = t2.sec();
+            HIP_TRY(hipEventRecord(p->pev[2], st));
             (prec == RBF_FP64 ? pt->mv64 : pt->mv32) += 1;
-            Timer t3;
-            // classical Gram-Schmidt, twice
-            double* h1 = p->hdev;
-            double* h2 = p->hdev + 64;
-            double* hn2 = p->hdev + 128;
-            HIP_TRY(rbf::launch_multidot(V, n, j + 1, p->w, n, p->partial, h1, st));
-            HIP_TRY(rbf::launch_multi_axpy(V, n, j + 1, h1, p->w, n, -1.0, st));
-            HIP_TRY(rbf::launch_multidot(V, n, j + 1, p->w, n, p->partial, h2, st));
-            HIP_TRY(rbf::launch_multi_axpy(V, n, j + 1, h2, p->w, n, -1.0, st));
-            HIP_TRY(rbf::launch_multidot(p->w, 0, 1, p->w, n, p->partial, hn2, st));
-            HIP_TRY(rbf::launch_scale_by_inv(p->w, hn2, V + (long long)(j + 1) * n, n, st));
-            HIP_TRY(hipMemcpyAsync(hh, p->hdev, sizeof(double) * (3 * 64 + 1) - sizeof(double) * 63,
-                                   hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            pt->vecmdot += t3.sec();
-            pt->matsolve += t_ms;
-            pt->matmult += t_mm;
+            RBF_TRY(gram_schmidt(p, j, st));
+            HIP_TRY(hipEventRecord(p->pev[3], st));
+            HIP_TRY(hipEventSynchronize(p->pev[3]));
+            pt->matsolve += 1e-3 * event_ms(p->pev[0], p->pev[1]);
+            pt->matmult += 1e-3 * event_ms(p->pev[1], p->pev[2]);
+            pt->vecmdot += 1e-3 * event_ms(p->pev[2], p->pev[3]);
+            const double* hh = p->hh;
             Timer t4;
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[64 + i];
             double hn = std::sqrt(hh[128]);
@@ -971,14 +1057,15 @@ rbf_status count_interactions(rbf_problem* p, int* d_nnb_sorted, hipStream_t st)
 
 rbf_status true_rel_residual(rbf_problem* p, const double* b, const double* x, double bnorm,
                              double* rel, hipStream_t st, PhaseTimes* pt) {
-    Timer t;
+    HIP_TRY(hipEventRecord(p->pev[0], st));
     RBF_TRY(matvec(p, RBF_FP64, x, p->w, st));
+    HIP_TRY(hipEventRecord(p->pev[1], st));
     pt->mv64 += 1;
     HIP_TRY(rbf::launch_sub(b, p->w, p->r, p->n, st));
     double r2;
-    RBF_TRY(norm2(p, p->r, &r2, st));
+    RBF_TRY(norm2(p, p->r, &r2, st));   // waits for the stream
     *rel = std::sqrt(r2) / bnorm;
-    pt->matmult += t.sec();
+    pt->matmult += 1e-3 * event_ms(p->pev[0], p->pev[1]);
     return RBF_OK;
 }
 
@@ -1470,6 +1557,12 @@ rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precisio
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_precond_block");
     }
+}
+
+rbf_status rbf_set_graphs(rbf_problem* p, int enable) {
+    if (!p) return fail(RBF_EINVAL, "NULL handle");
+    p->use_graphs = enable != 0;
+    return RBF_OK;
 }
 
 rbf_status rbf_set_profiling(rbf_problem* p, int enable) {
