@@ -511,8 +511,12 @@ rbf_status build_lists(rbf_problem* p, hipStream_t st) {
     RBF_TRY(p->alloc_n(&idx, ho[nu]));
     HIP_TRY(hipMemcpyAsync(off, ho.data(), sizeof(long long) * (nu + 1), hipMemcpyHostToDevice, st));
     HIP_TRY(rbf::launch_list_fill(a, nl, idx, st));
+    unsigned short* ordered = nullptr;
+    RBF_TRY(p->alloc_n(&ordered, ho[nu]));
+    HIP_TRY(rbf::launch_list_order(nl, idx, ordered, st));
     HIP_TRY(hipStreamSynchronize(st));
-    nl.idx = idx;
+    p->release(idx, st);
+    nl.idx = ordered;
     p->nl = nl;
     return RBF_OK;
 }
