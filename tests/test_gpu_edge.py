@@ -8,8 +8,10 @@ with empty cells (an annulus: cells with no own points build no block and
 own no rows), and the largest local blocks the workloads here reach (local
 blocks of up to 1444 points, n_p = 1472: 23 block columns of the
 factorisation; up to 169 points per cell: three passes of 64 right-hand
-sides in the centre-row solves), each against the oracle.  A local block
-above RBF_MAX_BLOCK is refused with RBF_ELIMIT.
+sides in the centre-row solves), each against the oracle.  A cell holding
+more targets than one workgroup of the list matvec serves (its targets split
+over two groups staging the same neighbourhood), against the oracle.  A local
+block above RBF_MAX_BLOCK is refused with RBF_ELIMIT.
 """
 import sys
 
@@ -219,5 +221,50 @@ def test_block_limit(torch_dev):
         with pytest.raises(R.RbfError) as e:
             R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-10))
         assert e.value.status == R.RBF_ELIMIT
+    finally:
+        R.rbf_destroy(h)
+
+
+def crowded_cell():
+    """A jittered 30x30 lattice (h/sigma = 0.8, cutoff 6 sigma: a 4x4 grid of
+    cells of ~56 points) plus 700 points drawn uniformly in a disk of radius
+    2 sigma at the centre of cell (1, 1): that cell holds ~756 targets, more
+    than one workgroup of the list matvec serves (8 units of 64), so its
+    targets are split over two groups that stage the same neighbourhood."""
+    pts, sigma = lattice(30, 0.8, 31)
+    cutoff = 6 * sigma
+    rng = np.random.default_rng(32)
+    x0, y0 = pts[:, 0].min(), pts[:, 1].min()
+    c = np.array([x0 + 1.5 * cutoff, y0 + 1.5 * cutoff])
+    r = 2 * sigma * np.sqrt(rng.uniform(0, 1, 700))
+    t = rng.uniform(0, 2 * np.pi, 700)
+    extra = c + np.stack([r * np.cos(t), r * np.sin(t)], 1)
+    return np.concatenate([pts, extra]), sigma, cutoff
+
+
+def test_cell_split_over_groups(torch_dev, oracle_mod):
+    torch = torch_dev
+    pts, sigma, cutoff = crowded_cell()
+    n = pts.shape[0]
+    say("crowded cell", n)
+    h = R.rbf_setup(pts, np.ones(n), sigma, cutoff, 1)
+    try:
+        P = oracle_mod.Problem(pts, sigma, cutoff, 1)
+        cell_of, _, cs = R.rbf_binning(h, n)
+        assert np.max(np.diff(cs)) > 512
+        nnb, _ = R.rbf_neighbor_counts(h, n)
+        _, o_nnb = P.matvec(np.ones(n), with_counts=True)
+        assert np.array_equal(nnb, o_nnb)
+        w = np.random.default_rng(33).uniform(-1, 1, n)
+        yo = P.matvec(w)
+        scale = P.matvec(np.abs(w))
+        y = gpu_matvec(torch, h, w)
+        assert np.max(np.abs(y - yo) / scale) <= 1e-13
+        dw = torch.tensor(w, device="cuda", dtype=torch.float64)
+        dy = torch.empty_like(dw)
+        R.rbf_matvec_device(h, dw, dy, R.RBF_MIXED, R.RBF_ORDER_ORIGINAL,
+                            torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        assert np.max(np.abs(dy.cpu().numpy() - yo) / scale) <= 2e-5
     finally:
         R.rbf_destroy(h)
