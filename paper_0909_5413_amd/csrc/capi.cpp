@@ -511,12 +511,8 @@ rbf_status build_lists(rbf_problem* p, hipStream_t st) {
     RBF_TRY(p->alloc_n(&idx, ho[nu]));
     HIP_TRY(hipMemcpyAsync(off, ho.data(), sizeof(long long) * (nu + 1), hipMemcpyHostToDevice, st));
     HIP_TRY(rbf::launch_list_fill(a, nl, idx, st));
-    unsigned short* ordered = nullptr;
-    RBF_TRY(p->alloc_n(&ordered, ho[nu]));
-    HIP_TRY(rbf::launch_list_order(nl, idx, ordered, st));
     HIP_TRY(hipStreamSynchronize(st));
-    p->release(idx, st);
-    nl.idx = ordered;
+    nl.idx = idx;
     p->nl = nl;
     return RBF_OK;
 }

@@ -280,45 +280,6 @@ __global__ __launch_bounds__(64 * kGroupMaxUnits) void k_list_build(MatvecArgs a
     }
 }
 
-// Reorders each lane's list (out of place) so that at a given step the lanes
-// of a unit tend to read staged records on distinct LDS banks: an entry
-// e = 16 q falls in class ((q mod 16) - lane) mod 16, and a lane's entries are
-// written class by class in ascending order (each class in its original
-// order).  Lanes with similar lists then sit in the same class at the same
-// step, which is a distinct residue q mod 16 for each of 16 consecutive lanes:
-// the records they read (16-byte coordinates at 16 q, 8-byte weights at 8 q)
-// fall on distinct banks.  Only the summation order of each target changes.
-__global__ __launch_bounds__(64) void k_list_order(const int* __restrict__ len,
-                                                   const long long* __restrict__ off,
-                                                   const unsigned short* __restrict__ in,
-                                                   unsigned short* __restrict__ out) {
-    __shared__ int start[16][64];
-    const int u = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int L = uniform(len[u]);
-    const unsigned short* src = in + off[u] + 4 * lane;
-    unsigned short* dst = out + off[u] + 4 * lane;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) start[c][lane] = 0;
-    for (int k = 0; k < L; ++k) {
-        const int c = ((src[256 * (k >> 2) + (k & 3)] >> 4) - lane) & 15;
-        ++start[c][lane];
-    }
-    int acc = 0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int m = start[c][lane];
-        start[c][lane] = acc;
-        acc += m;
-    }
-    for (int k = 0; k < L; ++k) {
-        const unsigned short e = src[256 * (k >> 2) + (k & 3)];
-        const int c = ((e >> 4) - lane) & 15;
-        const int to = start[c][lane]++;
-        dst[256 * (to >> 2) + (to & 3)] = e;
-    }
-}
-
 // LDS layout of the FP64 list matvec (a static allocation, so every address
 // offset is a compile-time constant): the staged weights W[q] at byte 8 q, the
 // coordinates (x, y)[q] at byte kXYBase + 16 q, so a list entry e = 16 q
@@ -523,12 +484,6 @@ hipError_t launch_list_fill(const MatvecArgs& a, const NeighborLists& nl, unsign
     if (nl.ngroups > 0)
         k_list_build<true><<<nl.ngroups, 64 * nl.gunits, 0, st>>>(a, nl, const_cast<int*>(nl.len),
                                                                    idx);
-    return hipGetLastError();
-}
-
-hipError_t launch_list_order(const NeighborLists& nl, const unsigned short* in,
-                             unsigned short* out, hipStream_t st) {
-    if (nl.nunits > 0) k_list_order<<<nl.nunits, 64, 0, st>>>(nl.len, nl.off, in, out);
     return hipGetLastError();
 }
 

@@ -132,10 +132,6 @@ hipError_t launch_list_count(const MatvecArgs& a, const NeighborLists& nl, int* 
                              hipStream_t st);
 hipError_t launch_list_fill(const MatvecArgs& a, const NeighborLists& nl, unsigned short* idx,
                             hipStream_t st);
-// Each lane's list rewritten from in to out with its entries ordered by bank
-// class (see k_list_order); same lengths and offsets.
-hipError_t launch_list_order(const NeighborLists& nl, const unsigned short* in,
-                             unsigned short* out, hipStream_t st);
 // The same products as launch_matvec64 / launch_matvec32 (targets = sources),
 // driven by the lists: every evaluated pair is an interaction.
 hipError_t launch_matvec64_lists(const MatvecArgs& a, const NeighborLists& nl, const double* w,
