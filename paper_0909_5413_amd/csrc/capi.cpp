@@ -711,44 +711,66 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     if (nslots > 8) nslots &= ~7LL;
     if (nslots < 1) nslots = 1;
     const long long pad = (nslots + 7) / 8 * 8;
-    T* scratch = nullptr;
-    T* lt = nullptr;
+    // Two lanes (two batches in flight on two streams) when there are two
+    // batches or more and their buffers fit; one when profiling, so that the
+    // per-kernel event times are those of kernels that run alone.
+    const long long nbatch = (nc + nslots - 1) / nslots;
+    int nlanes = (nbatch >= 2 && !p->profiling) ? 2 : 1;
+    rbf::SetupLane<T> lane[2] = {};
     int* status = nullptr;
-    int4* meta = nullptr;
-    int* lvl = nullptr;
-    double2* xy = nullptr;
-    rbf_status s = p->alloc_n(&scratch, nslots * slot_elems);
-    if (s == RBF_OK) s = p->alloc_n(&xy, pad * p->np_max);
-    if (s == RBF_OK) s = p->alloc_n(&status, nc);
-    if (s == RBF_OK) s = p->alloc_n(&meta, pad);
-    if (s == RBF_OK) s = p->alloc_n(&lvl, pad);
-    if (s == RBF_OK) s = p->alloc_n(&lt, 2 * pad * 2048);
-    auto release_all = [&]() {
-        if (scratch) p->release(scratch, st);
-        if (status) p->release(status, st);
-        if (meta) p->release(meta, st);
-        if (lvl) p->release(lvl, st);
-        if (lt) p->release(lt, st);
-        if (xy) p->release(xy, st);
+    hipStream_t st2 = nullptr;
+    auto alloc_lane = [&](rbf::SetupLane<T>& L) -> rbf_status {
+        RBF_TRY(p->alloc_n(&L.scratch, nslots * slot_elems));
+        RBF_TRY(p->alloc_n(&L.xy, pad * p->np_max));
+        RBF_TRY(p->alloc_n(&L.meta, pad));
+        RBF_TRY(p->alloc_n(&L.lvl, pad));
+        RBF_TRY(p->alloc_n(&L.lt, 2 * pad * 2048));
+        return RBF_OK;
     };
+    auto release_lane = [&](rbf::SetupLane<T>& L) {
+        if (L.scratch) p->release(L.scratch, st);
+        if (L.xy) p->release(L.xy, st);
+        if (L.meta) p->release(L.meta, st);
+        if (L.lvl) p->release(L.lvl, st);
+        if (L.lt) p->release(L.lt, st);
+        L = rbf::SetupLane<T>{};
+    };
+    auto release_all = [&]() {
+        release_lane(lane[0]);
+        release_lane(lane[1]);
+        if (status) p->release(status, st);
+    };
+    rbf_status s = p->alloc_n(&status, nc);
+    if (s == RBF_OK) s = alloc_lane(lane[0]);
     if (s != RBF_OK) {
         p->release(Z, st);
         release_all();
         return s;
     }
+    lane[0].st = st;
+    if (nlanes == 2) {
+        // the second lane is optional: without memory or a stream, one lane
+        if (alloc_lane(lane[1]) != RBF_OK ||
+            hipStreamCreateWithFlags(&st2, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            release_lane(lane[1]);
+            st2 = nullptr;
+            nlanes = 1;
+        }
+        lane[1].st = st2;
+    }
     rbf::PrecondArgs a = p->pc_args();
-    a.xy = xy;
     rbf::SetupProfile prof;
     rbf::SetupProfile* pp = p->profiling ? &prof : nullptr;
     hipError_t e;
     if (is64)
-        e = rbf::launch_precond_setup64(a, reinterpret_cast<double*>(Z),
-                                        reinterpret_cast<double*>(scratch), (int)nslots, meta,
-                                        reinterpret_cast<double*>(lt), lvl, status, st, pp);
+        e = rbf::launch_precond_setup64(a, reinterpret_cast<double*>(Z), (int)nslots,
+                                        reinterpret_cast<const rbf::SetupLane<double>*>(lane),
+                                        nlanes, status, st, pp);
     else
-        e = rbf::launch_precond_setup32(a, reinterpret_cast<float*>(Z),
-                                        reinterpret_cast<float*>(scratch), (int)nslots, meta,
-                                        reinterpret_cast<float*>(lt), lvl, status, st, pp);
+        e = rbf::launch_precond_setup32(a, reinterpret_cast<float*>(Z), (int)nslots,
+                                        reinterpret_cast<const rbf::SetupLane<float>*>(lane),
+                                        nlanes, status, st, pp);
     std::vector<int> hs(nc);
     if (e == hipSuccess)
         e = hipMemcpyAsync(hs.data(), status, sizeof(int) * nc, hipMemcpyDeviceToHost, st);
@@ -769,7 +791,12 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
         }
         p->ktimes_valid[pi] = e == hipSuccess;
     }
+    if (st2) {   // normally already joined into st; after an error perhaps not
+        (void)hipStreamSynchronize(st2);
+        (void)hipGetLastError();
+    }
     release_all();
+    if (st2) (void)hipStreamDestroy(st2);
     if (e != hipSuccess) {
         p->release(Z, st);
         return fail(RBF_EDEVICE, "preconditioner setup: %s", hipGetErrorString(e));

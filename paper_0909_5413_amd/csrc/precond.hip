@@ -1056,82 +1056,133 @@ __global__ __launch_bounds__(kZT, 3) void k_z_back(PrecondArgs a, long long c0, 
 // whose factorisation failed are rebuilt with the next diagonal shift (up to
 // four times), which needs the batch's status on the host.
 template <typename T>
-static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, T* scratch, int nslots, int4* meta,
-                                 T* lt, int* lvl, int* status, hipStream_t st,
-                                 SetupProfile* prof) {
+static hipError_t setup_lockstep(const PrecondArgs& a, T* Z, int nslots,
+                                 const SetupLane<T>* lanes, int nlanes, int* status,
+                                 hipStream_t st, SetupProfile* prof) {
     const int pad = (nslots + 7) / 8 * 8;
     const int ncp = (a.nc_max + kZCols - 1) / kZCols;
-    T* lt_buf[2] = {lt, lt + (size_t)pad * kLtElems};
     const int attempts = sizeof(T) == 4 ? 5 : 1;
     std::vector<int> hs;
     // every launch goes through here: with a profile, an event pair around it
     hipError_t perr = hipSuccess;
-    auto timed = [&](int kind, auto&& launch) {
+    auto timed = [&](int kind, hipStream_t ls, auto&& launch) {
         SetupProfile::Rec r{kind, nullptr, nullptr};
         if (prof && perr == hipSuccess) {
             perr = hipEventCreate(&r.start);
             if (perr == hipSuccess) perr = hipEventCreate(&r.stop);
-            if (perr == hipSuccess) perr = hipEventRecord(r.start, st);
+            if (perr == hipSuccess) perr = hipEventRecord(r.start, ls);
         }
         launch();
         if (prof && perr == hipSuccess) {
-            perr = hipEventRecord(r.stop, st);
+            perr = hipEventRecord(r.stop, ls);
             prof->recs.push_back(r);
         }
     };
-    for (long long c0 = 0; c0 < a.ncells; c0 += nslots) {
-        const int count = (int)(a.ncells - c0 < nslots ? a.ncells - c0 : nslots);
+    // lanes past the first start after the work already on st and st waits
+    // for them at the end
+    hipEvent_t join = nullptr;
+    if (nlanes > 1) {
+        hipError_t e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(join, st);
+        for (int l = 1; l < nlanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(lanes[l].st, join, 0);
+        if (e != hipSuccess) {
+            if (join) (void)hipEventDestroy(join);
+            return e;
+        }
+    }
+    const long long nbatch = (a.ncells + nslots - 1) / nslots;
+    for (long long b0 = 0; b0 < nbatch; b0 += nlanes) {
+        const int nl = (int)(nbatch - b0 < nlanes ? nbatch - b0 : nlanes);
+        long long c0[2];
+        PrecondArgs al[2];
+        for (int l = 0; l < nl; ++l) {
+            c0[l] = (b0 + l) * nslots;
+            al[l] = a;
+            al[l].xy = lanes[l].xy;
+        }
+        bool run[2] = {true, true};
         for (int att = 0; att < attempts; ++att) {
-            if (att > 0) {
-                hs.resize(count);
-                hipError_t e = hipMemcpyAsync(hs.data(), status + c0, sizeof(int) * count,
-                                              hipMemcpyDeviceToHost, st);
-                if (e == hipSuccess) e = hipStreamSynchronize(st);
-                if (e != hipSuccess) return e;
+            if (att > 0) {   // FP32: rebuild only the batches with failed blocks
                 bool any = false;
-                for (int v : hs) any |= v > 0;
+                for (int l = 0; l < nl; ++l) {
+                    const int count = (int)(a.ncells - c0[l] < nslots ? a.ncells - c0[l] : nslots);
+                    hs.resize(count);
+                    hipError_t e = hipMemcpyAsync(hs.data(), status + c0[l], sizeof(int) * count,
+                                                  hipMemcpyDeviceToHost, lanes[l].st);
+                    if (e == hipSuccess) e = hipStreamSynchronize(lanes[l].st);
+                    if (e != hipSuccess) return e;
+                    run[l] = false;
+                    for (int v : hs) run[l] = run[l] || v > 0;
+                    any = any || run[l];
+                }
                 if (!any) break;
             }
-            timed(RBF_K_ASSEMBLE, [&] {
-                k_setup_assemble<T><<<pad, kT2, 0, st>>>(a, c0, nslots, att > 0, scratch, meta,
-                                                         lvl, status, lt_buf[0]);
-            });
+            for (int l = 0; l < nl; ++l)
+                if (run[l])
+                    timed(RBF_K_ASSEMBLE, lanes[l].st, [&] {
+                        k_setup_assemble<T><<<pad, kT2, 0, lanes[l].st>>>(
+                            al[l], c0[l], nslots, att > 0, lanes[l].scratch, lanes[l].meta,
+                            lanes[l].lvl, status, lanes[l].lt);
+                    });
+            // the lanes' launches alternate, so one lane's narrow launches (the
+            // single-wave diagonal factors, the solves) share the device with the
+            // other lane's factorisation steps
             for (int J = 0; J + kFB < a.np_max; J += kFB) {
                 const int tiles = (a.np_max - J - kFB + kRows - 1) / kRows;
                 const int b = (J / kFB) & 1;
-                timed(RBF_K_CHOL_STEP, [&] {
-                    k_chol_step<T><<<pad * tiles, kTS, 0, st>>>(a, J, pad, scratch, meta,
-                                                                lt_buf[b]);
-                });
-                timed(RBF_K_CHOL_DIAG, [&] {
-                    k_chol_diag<T><<<pad, kDT, 0, st>>>(a, c0, J + kFB, scratch, meta, lvl,
-                                                        status, lt_buf[b ^ 1]);
-                });
+                for (int l = 0; l < nl; ++l)
+                    if (run[l])
+                        timed(RBF_K_CHOL_STEP, lanes[l].st, [&] {
+                            k_chol_step<T><<<pad * tiles, kTS, 0, lanes[l].st>>>(
+                                al[l], J, pad, lanes[l].scratch, lanes[l].meta,
+                                lanes[l].lt + (size_t)b * pad * kLtElems);
+                        });
+                for (int l = 0; l < nl; ++l)
+                    if (run[l])
+                        timed(RBF_K_CHOL_DIAG, lanes[l].st, [&] {
+                            k_chol_diag<T><<<pad, kDT, 0, lanes[l].st>>>(
+                                al[l], c0[l], J + kFB, lanes[l].scratch, lanes[l].meta,
+                                lanes[l].lvl, status, lanes[l].lt + (size_t)(b ^ 1) * pad * kLtElems);
+                        });
             }
             if (ncp > 0) {
-                timed(RBF_K_FORWARD, [&] {
-                    k_z_forward<T><<<pad * ncp, kT2, 0, st>>>(a, c0, pad, scratch, meta, Z);
-                });
-                timed(RBF_K_BACK, [&] {
-                    k_z_back<T><<<pad * ncp, kZT, 0, st>>>(a, c0, pad, scratch, meta, Z);
-                });
+                for (int l = 0; l < nl; ++l)
+                    if (run[l])
+                        timed(RBF_K_FORWARD, lanes[l].st, [&] {
+                            k_z_forward<T><<<pad * ncp, kT2, 0, lanes[l].st>>>(
+                                al[l], c0[l], pad, lanes[l].scratch, lanes[l].meta, Z);
+                        });
+                for (int l = 0; l < nl; ++l)
+                    if (run[l])
+                        timed(RBF_K_BACK, lanes[l].st, [&] {
+                            k_z_back<T><<<pad * ncp, kZT, 0, lanes[l].st>>>(
+                                al[l], c0[l], pad, lanes[l].scratch, lanes[l].meta, Z);
+                        });
             }
         }
     }
+    hipError_t e = hipGetLastError();
+    if (nlanes > 1) {
+        for (int l = 1; l < nlanes && e == hipSuccess; ++l) {
+            e = hipEventRecord(join, lanes[l].st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+        }
+        (void)hipEventDestroy(join);
+    }
     if (perr != hipSuccess) return perr;
-    return hipGetLastError();
+    return e;
 }
 
-hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scratch, int nslots,
-                                  int4* meta, double* lt, int* lvl, int* status, hipStream_t st,
-                                  SetupProfile* prof) {
-    return setup_lockstep<double>(a, Z, scratch, nslots, meta, lt, lvl, status, st, prof);
+hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, int nslots,
+                                  const SetupLane<double>* lanes, int nlanes, int* status,
+                                  hipStream_t st, SetupProfile* prof) {
+    return setup_lockstep<double>(a, Z, nslots, lanes, nlanes, status, st, prof);
 }
 
-hipError_t launch_precond_setup32(const PrecondArgs& a, float* Z, float* scratch, int nslots,
-                                  int4* meta, float* lt, int* lvl, int* status, hipStream_t st,
-                                  SetupProfile* prof) {
-    return setup_lockstep<float>(a, Z, scratch, nslots, meta, lt, lvl, status, st, prof);
+hipError_t launch_precond_setup32(const PrecondArgs& a, float* Z, int nslots,
+                                  const SetupLane<float>* lanes, int nlanes, int* status,
+                                  hipStream_t st, SetupProfile* prof) {
+    return setup_lockstep<float>(a, Z, nslots, lanes, nlanes, status, st, prof);
 }
 
 namespace {

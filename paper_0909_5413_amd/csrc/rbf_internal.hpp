@@ -173,11 +173,24 @@ struct SetupProfile {
     };
     std::vector<Rec> recs;
 };
-hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, double* scratch,
-                                  int nslots, int4* meta, double* lt, int* lvl, int* status,
+// One lane of the batched setup: a stream and the per-slot buffers of one
+// batch in flight (factor scratch, member coordinates, slot records, shift
+// levels, the two ping-pong diagonal-block buffers).  Batches go to the lanes
+// in turn; with two lanes, two batches advance together on two streams.
+template <typename T>
+struct SetupLane {
+    hipStream_t st;
+    T* scratch;
+    double2* xy;
+    int4* meta;
+    T* lt;
+    int* lvl;
+};
+hipError_t launch_precond_setup64(const PrecondArgs& a, double* Z, int nslots,
+                                  const SetupLane<double>* lanes, int nlanes, int* status,
                                   hipStream_t st, SetupProfile* prof);
-hipError_t launch_precond_setup32(const PrecondArgs& a, float* Z, float* scratch,
-                                  int nslots, int4* meta, float* lt, int* lvl, int* status,
+hipError_t launch_precond_setup32(const PrecondArgs& a, float* Z, int nslots,
+                                  const SetupLane<float>* lanes, int nlanes, int* status,
                                   hipStream_t st, SetupProfile* prof);
 // z[own points of c] = Z_c v[members of c], every cell.
 hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const double* v,
