@@ -263,6 +263,7 @@ struct rbf_problem {
     bool solved = false;
     rbf::NeighborLists nl{};           // matvec neighbour lists (nunits == 0: none)
     bool profiling = false;            // event timing of the setup launches
+    int setup_lanes = 2;               // batches of the factorisations in flight (1 or 2)
     // Arnoldi step: the Gram-Schmidt part of step j (two classical passes, the
     // norm, the normalisation and the read-back of the H column into pinned
     // host memory) as one captured graph per j, built on first use and kept
@@ -386,6 +387,12 @@ struct rbf_problem {
         return a;
     }
 };
+
+namespace rbf {
+void set_setup_lanes(rbf_problem* p, int lanes) {
+    if (p) p->setup_lanes = lanes > 1 ? 2 : 1;
+}
+}  // namespace rbf
 
 namespace rbf {
 hipError_t cached_alloc(int dev, size_t bytes, void** out, size_t* got) {
@@ -715,7 +722,7 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     // batches or more and their buffers fit; one when profiling, so that the
     // per-kernel event times are those of kernels that run alone.
     const long long nbatch = (nc + nslots - 1) / nslots;
-    int nlanes = (nbatch >= 2 && !p->profiling) ? 2 : 1;
+    int nlanes = (nbatch >= 2 && !p->profiling && p->setup_lanes > 1) ? 2 : 1;
     rbf::SetupLane<T> lane[2] = {};
     int* status = nullptr;
     hipStream_t st2 = nullptr;

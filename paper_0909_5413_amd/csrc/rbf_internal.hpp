@@ -7,6 +7,8 @@
 
 #include <vector>
 
+struct rbf_problem;
+
 namespace rbf {
 
 struct Grid {
@@ -197,6 +199,11 @@ hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const doub
                                double* z, hipStream_t st);
 hipError_t launch_rasm_apply32(const PrecondArgs& a, const float* Z, const double* v,
                                double* z, hipStream_t st);
+
+// Batches of a handle's local factorisations in flight together (1 or 2; 2 by
+// default).  The serving loop keeps its requests to one: they already overlap
+// one another on the device, and its admission counts one batch of scratch.
+void set_setup_lanes(rbf_problem* p, int lanes);
 
 // ---- device block cache (capi.cpp) -------------------------------------------
 // Allocation from, and return to, the library's cache of device blocks (see

@@ -144,6 +144,7 @@ struct rbf_server {
         }
         double* d_lam = static_cast<double*>(b_lam);
         if (s == RBF_OK) {
+            rbf::set_setup_lanes(h, 1);
             s = rbf_precond_setup(h, r->opts.precision, st);
             if (s != RBF_OK) msg = std::string("preconditioner: ") + rbf_last_error();
         }
