@@ -447,9 +447,6 @@ rbf_status build_lists(rbf_problem* p, hipStream_t st) {
             s += cs[(long long)ny * ncx + xhi + 1] - cs[(long long)ny * ncx + xlo];
         return s;
     };
-    int cells = rbf::kGroupCells;
-    if (const char* e = std::getenv("RBF_LIST_GROUP_CELLS")) cells = std::atoi(e);
-    cells = std::max(1, std::min(cells, rbf::kGroupCells));
     const int max_targets = 64 * rbf::kGroupMaxUnits;
     std::vector<rbf::ListGroup> groups;
     int nu = 0, max_nb = 0, gmax = 0;
@@ -477,7 +474,8 @@ rbf_status build_lists(rbf_problem* p, hipStream_t st) {
             }
             if (span(cy, cx, cx) > rbf::kListMaxNb) return RBF_OK;
             int cxb = cx;
-            while (cxb + 1 < ncx && cxb + 2 - cx <= cells && span(cy, cx, cxb + 1) <= rbf::kGroupSpan &&
+            while (cxb + 1 < ncx && cxb + 2 - cx <= rbf::kGroupCells &&
+                   span(cy, cx, cxb + 1) <= rbf::kGroupSpan &&
                    row[cxb + 2] - row[cx] <= max_targets)
                 ++cxb;
             if (row[cxb + 1] - row[cx] <= max_targets) {
