@@ -98,10 +98,14 @@ public:
         return (b + g - 1) / g * g;
     }
     // A block of at least `want` (rounded) and at most `limit` bytes; *got is
-    // its size.
+    // its size.  An idle block may be up to 1/8 larger than asked for, or up to
+    // 1/2 larger for blocks of 64 MiB and more: requests of a serving stream
+    // differ in size, and a miss on a large block (a fresh hipMalloc, ~15 ms,
+    // and sooner or later a hipFree that waits for the device) costs far more
+    // than the memory a larger idle block leaves unused while it is held.
     hipError_t alloc(int dev, size_t want, size_t limit, void** out, size_t* got) {
         const size_t r = round(want);
-        const size_t hi = std::min(limit, r + r / 8);
+        const size_t hi = std::min(limit, r >= (64u << 20) ? r + r / 2 : r + r / 8);
         Blk b{};
         bool found = false;
         {
