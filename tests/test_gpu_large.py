@@ -128,3 +128,41 @@ def test_c4_fp64_1e14_and_mixed_1e12(torch_dev, oracle_mod):
         say("c4", prec, "sampled matvec error / bar", err, "sampled residual", res)
         assert err <= 1e-13, err
         del lam, y
+
+
+@pytest.mark.timeout(300)
+def test_two_batches_in_flight_match_one(torch_dev):
+    """The local factorisations run two batches at once on two streams when a
+    problem has several batches; the profiled setup runs one at a time.  Both
+    must give the same centre rows bit for bit, in FP64 and in FP32 (whose
+    blocks that meet a non-positive pivot are rebuilt with a diagonal shift,
+    batch by batch), here on a 1000x1000 lattice at h/sigma = 0.6: 10^4 cells
+    of ~100 points, blocks of ~900, so several batches and shifted FP32 blocks."""
+    torch = torch_dev
+    w = W.Workload("lanes", 1000, 0.6, rtol=1e-12, seed=W.SEED_BASE + 9)
+    pts = w.points()
+    f = w.values(pts)
+    d_pts = torch.tensor(pts, device="cuda")
+    d_f = torch.tensor(f, device="cuda")
+    st = torch.cuda.current_stream()
+    for prec in (R.RBF_FP64, R.RBF_MIXED):
+        say("lanes", w.n, "precision", prec)
+        hs = []
+        try:
+            for one_at_a_time in (True, False):
+                h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, st)
+                hs.append(h)
+                R.rbf_set_profiling(h, one_at_a_time)
+                R.rbf_precond_setup(h, prec, st)
+            torch.cuda.synchronize()
+            _, (ncx, ncy) = R.rbf_grid(hs[0])
+            ncells = ncx * ncy
+            assert ncells > 8192
+            cells = sorted(set(list(range(0, ncells, 997)) + [4095, 4096, 8191, 8192, ncells - 1]))
+            for c in cells:
+                m0, z0 = R.rbf_precond_block(hs[0], c, prec)
+                m1, z1 = R.rbf_precond_block(hs[1], c, prec)
+                assert np.array_equal(m0, m1) and np.array_equal(z0, z1), c
+        finally:
+            for h in hs:
+                R.rbf_destroy(h)
