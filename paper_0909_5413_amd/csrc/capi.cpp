@@ -270,8 +270,9 @@ struct rbf_problem {
     int setup_lanes = 2;               // batches of the factorisations in flight (1 or 2)
     // Arnoldi step: the Gram-Schmidt part of step j (two classical passes, the
     // norm, the normalisation and the read-back of the H column into pinned
-    // host memory) as one captured graph per j, built on first use and kept
-    // while the workspace stands; events time the step's phases.
+    // host memory) as one captured graph per j (with rbf_set_graphs), built
+    // when step j comes round the second time and kept while the workspace
+    // stands; events time the step's phases.
     hipStream_t gstream = nullptr;     // capture stream (default priority)
     std::vector<hipGraphExec_t> gs_exec;
     std::vector<int> gs_uses;          // launches of step j's work so far
@@ -396,9 +397,7 @@ namespace rbf {
 void set_setup_lanes(rbf_problem* p, int lanes) {
     if (p) p->setup_lanes = lanes > 1 ? 2 : 1;
 }
-}  // namespace rbf
 
-namespace rbf {
 hipError_t cached_alloc(int dev, size_t bytes, void** out, size_t* got) {
     return BlockCache::get().alloc(dev, bytes, (size_t)-1, out, got);
 }
