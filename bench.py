@@ -343,14 +343,37 @@ def main():
         try:
             R.rbf_precond_setup(h, R.RBF_MIXED, stream)
             minfo, mst = R.rbf_solve_device(h, d_lam, mopts, ok=(R.RBF_OK, R.RBF_ENOCONV))
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - t1
+            # the interpolant at the staggered lattice between the nodes, against
+            # the closed-form data and the FP64 interpolant (evaluated below)
+            tg = W.staggered_lattice(w.n_side)
+            d_tg = torch.tensor(tg, device=dev)
+            s_mx = torch.empty(tg.shape[0], device=dev, dtype=torch.float64)
+            R.rbf_evaluate_device(h, d_tg, tg.shape[0], s_mx, stream)
         finally:
             R.rbf_destroy(h)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t1
         werr = float(torch.linalg.norm(d_lam - lam64) / torch.linalg.norm(lam64))
+        h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+        try:
+            R.rbf_precond_setup(h, R.RBF_FP64, stream)
+            R.rbf_solve_device(h, d_lam, opts)
+            s_64 = torch.empty_like(s_mx)
+            R.rbf_evaluate_device(h, d_tg, tg.shape[0], s_64, stream)
+            t_ev = event_time(torch, stream, lambda: R.rbf_evaluate_device(
+                h, d_tg, tg.shape[0], s_64, stream), 5)
+        finally:
+            R.rbf_destroy(h)
+        fex = torch.tensor(W.gaussian_vortex(tg, w.r0), device=dev)
+        fmax = float(fex.abs().max())
         mixed = {"s_to_tol": tm, "status": R.status_name(mst),
                  "iterations_inner": minfo.iterations, "outer": minfo.outer_iterations,
-                 "rel_residual": minfo.rel_residual, "weight_rel_diff_vs_fp64": werr}
+                 "rel_residual": minfo.rel_residual, "weight_rel_diff_vs_fp64": werr,
+                 "interpolant_points": int(tg.shape[0]),
+                 "interp_err_fp64": float((s_64 - fex).abs().max()) / fmax,
+                 "interp_err_mixed": float((s_mx - fex).abs().max()) / fmax,
+                 "interp_rel_diff_mixed_vs_fp64": float((s_mx - s_64).abs().max() / s_64.abs().max()),
+                 "evaluate_ms": t_ev, "evaluations_per_s": tg.shape[0] / (t_ev * 1e-3)}
         log("mixed", mixed)
 
     serving = None
