@@ -795,29 +795,46 @@ __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int 
         step_tile<T, 1>(A, xy, p, a.mk, a.norm, J, k0, R, wave, s);
 }
 
-// Diagonal block J0 > 0 of every slot, one wave per slot: D = A[J0.., J0..] -
-// L[J0.., k0:J0] L[J0.., k0:J0]^T on its ten lower 16x16 tiles (MFMA chains,
-// operands in two register buffers), then its factor (factor_diag64) into A
-// and lt_out.
-constexpr int kDT = 64;
+// Diagonal block J0 > 0 of every slot, one workgroup of two waves per slot:
+// D = A[J0.., J0..] - L[J0.., k0:J0] L[J0.., k0:J0]^T on its ten lower 16x16
+// tiles.  The 16-column chunks of k0:J0 are dealt to the waves in pairs (wave
+// w takes pairs w, w + 2, ...; MFMA chains, operands in two register buffers);
+// wave 0 writes the evaluated block minus its sums, then wave 1 subtracts
+// its own, so the order of the additions is fixed.  Then the block's factor
+// (factor_diag64, on wave 0) into A and lt_out.  Two waves, not four: the
+// serial factor runs on one wave, and six two-wave workgroups fit a CU's LDS
+// where four-wave ones would leave fewer slots per CU in that phase.
+constexpr int kDT = 128;
+constexpr int kDW = kDT / 64;
 
 template <typename T>
-__global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, int J0,
-                                                   T* __restrict__ scratch,
-                                                   int4* __restrict__ meta,
-                                                   const int* __restrict__ lvl,
-                                                   int* __restrict__ status,
-                                                   T* __restrict__ lt_out) {
+__device__ __forceinline__ void diag64_sub(Diag64<T>& d, int r, int c, T v) {
+    if (r < kNB)
+        d.D11[r][c] -= v;
+    else if (c < kNB)
+        d.D21[r - kNB][c] -= v;
+    else
+        d.D22[r - kNB][c - kNB] -= v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDT, 2) void k_chol_diag(PrecondArgs a, long long c0, int J0,
+                                                      T* __restrict__ scratch,
+                                                      int4* __restrict__ meta,
+                                                      const int* __restrict__ lvl,
+                                                      int* __restrict__ status,
+                                                      T* __restrict__ lt_out) {
     __shared__ Diag64<T> s;
+    __shared__ double2 xd[kFB];   // coordinates of the block's 64 rows
     const int slot = blockIdx.x;
     const int4 m = meta[slot];
     const int np = m.x;
     if (!m.w || J0 >= np) return;
-    const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, i16 = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
     const int k0 = (np - m.y) / kNB * kNB;
-    __shared__ double2 xd[kFB];   // coordinates of the block's 64 rows
-    xd[lane] = a.xy[(size_t)slot * a.np_max + J0 + lane];
+    if (tid < kFB) xd[tid] = a.xy[(size_t)slot * a.np_max + J0 + tid];
     const double shift = sizeof(T) == 4 ? diag_shift(lvl[slot], m.y, a.norm) : 0.0;
     const T* rows[4];
 #pragma unroll
@@ -836,38 +853,47 @@ __global__ __launch_bounds__(kDT) void k_chol_diag(PrecondArgs a, long long c0, 
         }
     };
     const int nchunk = (J0 - k0) / 16;   // even, >= 2
-    v4<T> p[4], q[4];
+    int ch = 2 * wave;
+    if (ch < nchunk) {
+        v4<T> p[4], q[4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) p[x] = load4(rows[x]);
-    for (int ch = 0; ch < nchunk; ch += 2) {
+        for (int x = 0; x < 4; ++x) p[x] = load4(rows[x] + 16 * ch);
+        for (; ch < nchunk; ch += 2 * kDW) {
 #pragma unroll
-        for (int x = 0; x < 4; ++x) q[x] = load4(rows[x] + 16 * (ch + 1));
-        mma10(p);
-        if (ch + 2 < nchunk) {
+            for (int x = 0; x < 4; ++x) q[x] = load4(rows[x] + 16 * (ch + 1));
+            mma10(p);
+            if (ch + 2 * kDW < nchunk) {
 #pragma unroll
-            for (int x = 0; x < 4; ++x) p[x] = load4(rows[x] + 16 * (ch + 2));
+                for (int x = 0; x < 4; ++x) p[x] = load4(rows[x] + 16 * (ch + 2 * kDW));
+            }
+            mma10(q);
         }
-        mma10(q);
     }
     __syncthreads();   // the staged coordinates
-    {
-        int t = 0;
+    for (int w = 0; w < kDW; ++w) {
+        if (wave == w && (w == 0 || 2 * w < nchunk)) {
+            int t = 0;
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y <= x; ++y, ++t)
+                for (int y = 0; y <= x; ++y, ++t)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * x + out_row<T>(g, v), c = 16 * y + i16;
-                    // rows J0 + r >= 64 lie past the padding (fewer than 64 rows)
-                    diag64_put<T>(s, r, c,
-                                  gauss_entry<T>(xd[r], xd[c], r == c, a.mk, a.norm, shift) -
-                                      acc[t][v]);
-                }
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * x + out_row<T>(g, v), c = 16 * y + i16;
+                        // rows J0 + r >= 64 lie past the padding (fewer than 64 rows)
+                        if (w == 0)
+                            diag64_put<T>(s, r, c,
+                                          gauss_entry<T>(xd[r], xd[c], r == c, a.mk, a.norm,
+                                                         shift) -
+                                              acc[t][v]);
+                        else
+                            diag64_sub<T>(s, r, c, acc[t][v]);
+                    }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int f = factor_diag64<T>(A, J0, s, lt_out + (size_t)slot * kLtElems);
-    if (f && lane == 0) {
+    if (f && tid == 0) {
         status[c0 + slot] = f;
         meta[slot].w = 0;
     }
