@@ -677,6 +677,41 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
     }
 }
 
+// Stage what the panel solve of a step tile needs in LDS: the diagonal 32x32
+// blocks of L_JJ (transposed, packed, reciprocal pivots) from lt, the coupling
+// block L21 from A, and the member coordinates of the tile's rows and of the
+// block column.
+template <typename T>
+__device__ __forceinline__ void stage_step(const T* __restrict__ A, const T* __restrict__ lt,
+                                           const double2* __restrict__ xy, int np, int J, int R,
+                                           StepLds<T>& s) {
+    const int tid = threadIdx.x;
+    constexpr int kE = kNB * kNB / kTS;
+    T l1[kE], l2[kE], l21[kE];
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+        const int e = tid + kTS * q, k = e / kNB, j = e % kNB;
+        l1[q] = lt[e];
+        l2[q] = lt[kNB * kNB + e];
+        l21[q] = A[roff(J + kNB + k) + J + j];
+    }
+    const int nrow = np - R < kRows ? np - R : kRows;
+    double2 xr = {0.0, 0.0}, xc = {0.0, 0.0};
+    if (tid < nrow) xr = xy[R + tid];
+    if (tid < kFB) xc = xy[J + tid];
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+        const int e = tid + kTS * q, k = e / kNB, j = e % kNB;
+        if (j >= k) {
+            s.Lt1[tri(k, j)] = l1[q];
+            s.Lt2[tri(k, j)] = l2[q];
+        }
+        s.L21[k][j] = l21[q];
+    }
+    if (tid < nrow) s.xr[tid] = xr;
+    if (tid < kFB) s.xc[tid] = xc;
+}
+
 // One step tile: rows R .. R + 16 kWS M - 1 of block column J.  The update
 // (MFMA, registers; the accumulators start from -A so that they end as the
 // negated updated tile, and the loads of A overlap the update), then the
@@ -684,7 +719,8 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
 // substitution, a2 -= x1 L21^T on MFMA into the update's accumulators,
 // x2 = a2 L22^-T; both halves pass through LDS once.
 template <typename T, int M>
-__device__ __forceinline__ void step_tile(T* __restrict__ A, const double2* __restrict__ xy, int p,
+__device__ __forceinline__ void step_tile(T* __restrict__ A, const T* __restrict__ lt,
+                                          const double2* __restrict__ xy, int np, int p,
                                           double mk, double norm, int J, int k0, int R, int wave,
                                           StepLds<T>& s) {
     constexpr int nrow = 16 * kWS * M;
@@ -695,11 +731,12 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const double2* __re
     for (int t = 0; t < M; ++t)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) u.acc[t][cb] = v4<T>{0, 0, 0, 0};
-    if (J > 0) {
-        u.prologue(A, J, k0, R, wave);
-        u.update(J, k0);
-    }
-    __syncthreads();   // the staged coordinates
+    // the update's first operand loads go out before the staging loads, so
+    // the two wait for memory together
+    if (J > 0) u.prologue(A, J, k0, R, wave);
+    stage_step<T>(A, lt, xy, np, J, R, s);
+    if (J > 0) u.update(J, k0);
+    __syncthreads();   // the staged blocks and coordinates
 #pragma unroll
     for (int t = 0; t < M; ++t)
 #pragma unroll
@@ -758,41 +795,15 @@ __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int 
     const int tid = threadIdx.x;
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
     const T* lt = lt_in + (size_t)slot * kLtElems;
-    {
-        constexpr int kE = kNB * kNB / kTS;
-        T l1[kE], l2[kE], l21[kE];
-#pragma unroll
-        for (int q = 0; q < kE; ++q) {
-            const int e = tid + kTS * q, k = e / kNB, j = e % kNB;
-            l1[q] = lt[e];
-            l2[q] = lt[kNB * kNB + e];
-            l21[q] = A[roff(J + kNB + k) + J + j];
-        }
-#pragma unroll
-        for (int q = 0; q < kE; ++q) {
-            const int e = tid + kTS * q, k = e / kNB, j = e % kNB;
-            if (j >= k) {
-                s.Lt1[tri(k, j)] = l1[q];
-                s.Lt2[tri(k, j)] = l2[q];
-            }
-            s.L21[k][j] = l21[q];
-        }
-    }
-    {
-        const double2* xy = a.xy + (size_t)slot * a.np_max;
-        const int nrow = np - R < kRows ? np - R : kRows;
-        if (tid < nrow) s.xr[tid] = xy[R + tid];
-        if (tid < kFB) s.xc[tid] = xy[J + tid];
-    }
     // rows at or past the padding are zero in the padding columns
     const int k0 = (np - m.y) / kNB * kNB;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double2* xy = a.xy + (size_t)slot * a.np_max;
     const int p = np - m.y;
     if (np - R >= kRows)
-        step_tile<T, 2>(A, xy, p, a.mk, a.norm, J, k0, R, wave, s);
+        step_tile<T, 2>(A, lt, xy, np, p, a.mk, a.norm, J, k0, R, wave, s);
     else
-        step_tile<T, 1>(A, xy, p, a.mk, a.norm, J, k0, R, wave, s);
+        step_tile<T, 1>(A, lt, xy, np, p, a.mk, a.norm, J, k0, R, wave, s);
 }
 
 // Diagonal block J0 > 0 of every slot, one workgroup of two waves per slot:
