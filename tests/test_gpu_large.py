@@ -131,6 +131,81 @@ def test_c4_fp64_1e14_and_mixed_1e12(torch_dev, oracle_mod):
 
 
 @pytest.mark.timeout(300)
+def test_c1_bench_workload(torch_dev, oracle_mod):
+    """The benchmarked workload (N = 10^6 jittered lattice, h/sigma = 0.8) in the
+    benchmark's launch configuration: setup on the device, the preconditioner
+    built with two factorisation batches in flight, the solve to 1e-12, for
+    FP64 and mixed precision.  Judged by the true residual from the GPU matvec,
+    that matvec against the oracle on 2000 sampled rows, the centre rows Z_c of
+    sampled cells (first, interior, around the factorisation batch boundaries,
+    last) as rows of the inverse of the dense local matrix (backward error, as
+    in the small parity cases), and the RASM apply on those cells' points
+    against Z_c v[members] formed in numpy from the same rows."""
+    torch = torch_dev
+    from tests import bruteforce as bf
+    w = W.WORKLOADS["c1"]
+    pts = w.points()
+    f = w.values(pts)
+    d_pts = torch.tensor(pts, device="cuda")
+    d_f = torch.tensor(f, device="cuda")
+    v = W.random_weights(w.n, 17)
+    d_v = torch.tensor(v, device="cuda")
+    st = torch.cuda.current_stream()
+    u, u32 = np.finfo(float).eps / 2, 2.0 ** -24
+    phi0 = 1.0 / (2 * np.pi * w.sigma * w.sigma)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff, w.overlap)
+    h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, st)
+    try:
+        _, (ncx, ncy) = R.rbf_grid(h)
+        ncells = ncx * ncy
+        cells = sorted(c for c in {0, ncx + 1, 8191, 8192, 16383, 16384, ncells // 2, ncells - 1}
+                       if c < ncells)
+        for prec in (R.RBF_FP64, R.RBF_MIXED):
+            say("c1 precision", prec, "N", w.n, "cells", cells)
+            R.rbf_precond_setup(h, prec, st)
+            lam = torch.empty(w.n, device="cuda", dtype=torch.float64)
+            info, status = R.rbf_solve_device(h, lam, R.default_opts(rtol=1e-12, precision=prec,
+                                                                    stream=st))
+            y = torch.empty_like(lam)
+            R.rbf_matvec_device(h, lam, y, R.RBF_FP64, R.RBF_ORDER_ORIGINAL, st)
+            d_z = torch.empty_like(d_v)
+            R.rbf_precond_apply_device(h, d_v, d_z, prec, R.RBF_ORDER_ORIGINAL, st)
+            torch.cuda.synchronize()
+            lam_h, y_h, z_h = lam.cpu().numpy(), y.cpu().numpy(), d_z.cpu().numpy()
+            assert status == R.RBF_OK, info.as_dict()
+            assert info.rel_residual <= 1.05e-12, info.as_dict()
+            assert np.linalg.norm(f - y_h) / np.linalg.norm(f) <= 1.05e-12
+            err, res = sampled_rows(oracle_mod, pts, w, lam_h, y_h, f, 2000, 21 + prec)
+            say("c1", prec, "iterations", info.iterations, "sampled matvec error / bar", err)
+            assert err <= 1e-13, err
+            assert res <= 1e-10, res
+            for cell in cells:
+                mem, Z = R.rbf_precond_block(h, cell, prec)
+                o_mem, kc, _ = P.rasm_block(cell, with_factor=False)
+                assert np.array_equal(mem, o_mem), cell
+                if Z.shape[0] == 0:
+                    continue
+                Z = Z.astype(np.float64)
+                A = bf.dense_matrix(pts[mem], w.sigma, None)
+                n = len(mem)
+                back = np.linalg.norm(Z @ A - np.eye(n)[n - kc:], 2)
+                if prec == R.RBF_FP64:
+                    bound = 10 * n * u * np.linalg.norm(Z, 2) * np.linalg.norm(A, 2)
+                else:
+                    bound = (10 * n * u32 * np.linalg.norm(A, 2) + 1000 * n * u32 * phi0) * \
+                        np.linalg.norm(Z, 2)
+                assert back <= bound, (cell, back, bound)
+                # the apply on this cell's own points, from the same rows; the
+                # FP32 form multiplies by v rounded to FP32
+                ref = Z @ v[mem]
+                scale = np.abs(Z) @ np.abs(v[mem])
+                tol = 4 * n * u if prec == R.RBF_FP64 else 4 * u32
+                assert np.max(np.abs(z_h[mem[n - kc:]] - ref) / scale) <= tol, cell
+    finally:
+        R.rbf_destroy(h)
+
+
+@pytest.mark.timeout(300)
 def test_two_batches_in_flight_match_one(torch_dev):
     """The local factorisations run two batches at once on two streams when a
     problem has several batches; the profiled setup runs one at a time.  Both
