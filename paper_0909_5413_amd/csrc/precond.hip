@@ -190,73 +190,98 @@ __device__ __forceinline__ size_t roff(int row) {
 
 // The update of a step tile: acc[t][cb] += sum_{k0 <= k < J} L[row][k] L[J + 16 cb + col][k]
 // for the wave's row tiles t (rows R + 16 (wave + 4 t) ..) and the four 16-column
-// tiles of the block column.  MFMA tiles with no LDS staging and no barriers:
-// the contraction index of an MFMA may be permuted as long as A and B use the
-// same permutation, so over a chunk of 16 k values lane group g = l/16 owns
-// k = K+4g .. K+4g+3 and loads them from its row with one vector load; step s
-// of the chunk uses element s.  Each wave loads its own M row tiles (three
-// register buffers: two chunks in flight while one is multiplied) and the four
-// column tiles (shared by the waves through the caches; two buffers).  Six
-// chunks per loop pass keep every buffer index a constant and the body free of
-// branches, so each multiply waits only for its own loads.  Columns below k0
+// tiles of the block column, as MFMA tiles.  The contraction index of an MFMA
+// may be permuted as long as A and B use the same permutation, so over a chunk
+// of 16 k values lane group g = l/16 owns k = K+4g .. K+4g+3 and loads them
+// from its row with one vector load; step s of the chunk uses element s.  Each
+// wave loads its own M row tiles straight into registers (two register
+// buffers: the next chunk in flight while one is multiplied).  The 64 block rows
+// J .. J + 63, which every wave multiplies with, are loaded once per workgroup
+// (one vector load per thread and chunk, a chunk ahead) into an LDS buffer of
+// two chunks, where each wave reads its operands; one barrier per chunk.  Six
+// chunks per loop pass keep every buffer index a constant.  Columns below k0
 // are zero in every row involved (leading identity padding) and are skipped.
+// A staged chunk row of 16 values is padded to 18 doubles (20 floats), so rows
+// start 16 bytes apart modulo 128 and the 16 rows a read instruction touches
+// spread over the LDS banks; every row start stays 16-byte aligned.
+template <typename T>
+constexpr int kBS = sizeof(T) == 8 ? 18 : 20;
+
 template <typename T, int M>
-struct UpdateRegs {
-    v4<T> a[3][M];
-    v4<T> b[2][4];
+struct StepUpdate {
+    static_assert(2 * 64 * kBS<T> <= kNB * kXS, "two staged chunks fit in the tile buffer");
+    v4<T> a[2][M];
     v4<T> acc[M][4];
+    v4<T> bst;             // this thread's part of the next chunk of the block rows
     const T* arow[M];
-    const T* brow[4];
+    const T* bsrc;         // row J + tid / 4, k = k0 + 4 (tid % 4)
+    T (*bs)[64][kBS<T>];   // two chunk buffers in LDS
 
     __device__ __forceinline__ void load_a(int buf, int ch) {
 #pragma unroll
         for (int t = 0; t < M; ++t) a[buf][t] = load4(arow[t] + 16 * ch);
     }
-    __device__ __forceinline__ void load_b(int buf, int ch) {
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) b[buf][cb] = load4(brow[cb] + 16 * ch);
+    __device__ __forceinline__ void load_b(int ch) { bst = load4(bsrc + 16 * ch); }
+    __device__ __forceinline__ void store_b(int buf) {
+        const int tid = threadIdx.x;
+        T* d = &bs[buf][tid >> 2][4 * (tid & 3)];
+        *reinterpret_cast<v2<T>*>(d) = v2<T>{bst[0], bst[1]};
+        *reinterpret_cast<v2<T>*>(d + 2) = v2<T>{bst[2], bst[3]};
     }
     __device__ __forceinline__ void mma(int ba, int bb) {
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, g = lane >> 4;
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
+            T b[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) b[cb] = bs[bb][16 * cb + i16][4 * g + st];
 #pragma unroll
             for (int t = 0; t < M; ++t) {
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb)
-                    acc[t][cb] = mfma(a[ba][t][st], b[bb][cb][st], acc[t][cb]);
+                    acc[t][cb] = mfma(a[ba][t][st], b[cb], acc[t][cb]);
             }
         }
     }
-    // chunks c .. c + min(R, 6) - 1; on entry chunks c, c + 1 of A and chunk c
-    // of B are loaded (c is a multiple of 6), no load reaches c + R
+    // chunks c .. c + min(R, 6) - 1; on entry chunk c of A is in a[0], chunk c
+    // of the block rows in bs[0] and chunk c + 1 in bst (c is a multiple of 6);
+    // no load reaches c + R
     template <int R>
     __device__ __forceinline__ void run(int c) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             if (i < R) {
-                if (i + 2 < R) load_a((i + 2) % 3, c + i + 2);
-                if (i + 1 < R) load_b((i + 1) % 2, c + i + 1);
-                mma(i % 3, i % 2);
+                if (i + 1 < R) load_a((i + 1) % 2, c + i + 1);
+                mma(i % 2, i % 2);
+                if (i + 1 < R) {
+                    store_b((i + 1) % 2);
+                    if (i + 2 < R) load_b(c + i + 2);
+                }
+                __syncthreads();
             }
         }
     }
     // the first loads of the update (J > 0)
     __device__ __forceinline__ void prologue(const T* __restrict__ A, int J, int k0, int R,
-                                             int wave) {
-        const int lane = threadIdx.x & 63;
+                                             int wave, T* lds) {
+        const int tid = threadIdx.x, lane = tid & 63;
         const int i16 = lane & 15, g = lane >> 4;
+        bs = reinterpret_cast<T (*)[64][kBS<T>]>(lds);
 #pragma unroll
         for (int t = 0; t < M; ++t) arow[t] = A + roff(R + 16 * (wave + kWS * t) + i16) + k0 + 4 * g;
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) brow[cb] = A + roff(J + 16 * cb + i16) + k0 + 4 * g;
+        bsrc = A + roff(J + (tid >> 2)) + k0 + 4 * (tid & 3);
         load_a(0, 0);
-        load_a(1, 1);
-        load_b(0, 0);
+        load_b(0);
     }
     // acc[t][cb] += the products over (J - k0) / 16 chunks (J > 0; after the
-    // prologue; the caller initialises acc)
+    // prologue; the caller initialises acc).  The chunk buffers borrow the
+    // tile's LDS buffer, which is free again after the last chunk's barrier.
     __device__ __forceinline__ void update(int J, int k0) {
         const int nchunk = (J - k0) / 16;   // >= 2, even
+        store_b(0);
+        load_b(1);
+        __syncthreads();
         int c = 0;
         for (; c + 8 <= nchunk; c += 6) run<99>(c);
         const int rest = nchunk - c;   // 2, 4 or 6
@@ -726,14 +751,15 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const T* __restrict
     constexpr int nrow = 16 * kWS * M;
     const int lane = threadIdx.x & 63;
     const int i16 = lane & 15, g = lane >> 4;
-    UpdateRegs<T, M> u;
+    StepUpdate<T, M> u;
 #pragma unroll
     for (int t = 0; t < M; ++t)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) u.acc[t][cb] = v4<T>{0, 0, 0, 0};
     // the update's first operand loads go out before the staging loads, so
-    // the two wait for memory together
-    if (J > 0) u.prologue(A, J, k0, R, wave);
+    // the two wait for memory together; the update stages its block rows in
+    // s.X, which the panel solve needs only afterwards
+    if (J > 0) u.prologue(A, J, k0, R, wave, &s.X[0][0]);
     stage_step<T>(A, lt, xy, np, J, R, s);
     if (J > 0) u.update(J, k0);
     __syncthreads();   // the staged blocks and coordinates
