@@ -102,7 +102,8 @@ __device__ __forceinline__ int member_index(const int* rb, const int* re, int nr
 // launch for the forward solve on the trailing rows, one launch per block row
 // of the back solve.  Every launch carries thousands of independent
 // workgroups, so one cell's serial steps overlap with other cells' work.
-// Workgroup b serves slot b % nslots_pad (a multiple of 8): a slot's
+// Workgroup b serves slot b % nslots_pad (a multiple of 8; the step launch
+// orders its tiles differently, with the same slot-to-XCD map): a slot's
 // workgroups run on one XCD in every launch, and its rows stay in that XCD's
 // L2 from launch to launch.
 // MFMA tiles are 16x16x4 (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32).  On
@@ -171,6 +172,7 @@ constexpr int kRows = 128;      // rows per step tile
 static_assert(kRows <= kTS, "the substitution gives one row to each thread");
 static_assert(kRows == 2 * 16 * kWS, "two row tiles per wave in a full tile");
 constexpr int kXS = kRows + 1;  // padded LDS row of a staged tile (conflict-free MFMA stores)
+constexpr int kTileGroup = 16;  // slots whose step tiles are interleaved on an XCD
 constexpr int kTri = kNB * (kNB + 1) / 2;
 constexpr int kLtElems = 2 * kNB * kNB;   // per slot: both diagonal 32x32 blocks of L_JJ
 
@@ -804,16 +806,40 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const T* __restrict
     store_tile<T>(A, J + kNB, R, nrow, s.X);
 }
 
-// Block column J (64 columns): workgroup b takes the 128-row tile
-// b / nslots_pad below the diagonal block of slot b % nslots_pad.  lt_in: per
-// slot, the diagonal 32x32 blocks of L_JJ transposed with reciprocal pivots.
+// Block column J (64 columns): the launch has nslots_pad x tiles workgroups,
+// one per (slot, 128-row tile below the slot's diagonal block), ordered as
+// below.  lt_in: per slot, the diagonal 32x32 blocks of L_JJ transposed with
+// reciprocal pivots.
 template <typename T>
 __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int nslots_pad,
                                                       T* __restrict__ scratch,
                                                       const int4* __restrict__ meta,
                                                       const T* __restrict__ lt_in) {
     __shared__ StepLds<T> s;
-    const int slot = blockIdx.x % nslots_pad, tile = blockIdx.x / nslots_pad;
+    // workgroup b runs on XCD b % 8 and serves a slot of that XCD (slot % 8 ==
+    // b % 8, as in the other setup kernels); along each XCD's sequence of
+    // workgroups the tiles of groups of kTileGroup slots are interleaved, so a
+    // slot's tiles run close together in time and share its block rows
+    // through that XCD's L2
+    int slot, tile;
+    {
+        const int tiles = gridDim.x / nslots_pad;
+        const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
+        const int per = nslots_pad >> 3, full = per / kTileGroup, span = kTileGroup * tiles;
+        int grp, j;
+        if (q < full * span) {
+            grp = q / span;
+            const int r = q - grp * span;
+            tile = r / kTileGroup;
+            j = r - tile * kTileGroup;
+        } else {   // the last, smaller group
+            const int gl = per - full * kTileGroup, r = q - full * span;
+            grp = full;
+            tile = r / gl;
+            j = r - tile * gl;
+        }
+        slot = 8 * (grp * kTileGroup + j) + x;
+    }
     const int4 m = meta[slot];
     const int np = m.x;
     const int R = J + kFB + kRows * tile;
