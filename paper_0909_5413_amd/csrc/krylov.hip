@@ -113,18 +113,23 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const double* __restric
     if (bad) atomicOr(flag, 1);
 }
 
+// Sum of n non-negative counts into out[0], which the caller zeroes: a
+// grid-stride pass, a workgroup reduction, one 64-bit atomic add per
+// workgroup (integer sums are exact in any order).
 __global__ __launch_bounds__(kBlock) void k_sum_counts(const int* __restrict__ c, long long n,
-                                                       long long* __restrict__ out) {
-    __shared__ long long sh[kBlock];
-    long long v = 0;
-    for (long long i = threadIdx.x; i < n; i += kBlock) v += c[i];
+                                                       unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long sh[kBlock];
+    unsigned long long v = 0;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock)
+        v += (unsigned long long)c[i];
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int o = kBlock / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = sh[0];
+    if (threadIdx.x == 0 && sh[0] != 0) atomicAdd(out, sh[0]);
 }
 
 inline unsigned stream_grid(long long n) {
@@ -194,7 +199,10 @@ hipError_t launch_check_finite(const double* x, long long n, int* flag, hipStrea
 }
 
 hipError_t launch_sum_counts(const int* nnb, long long n, long long* out, hipStream_t st) {
-    k_sum_counts<<<1, kBlock, 0, st>>>(nnb, n, out);
+    hipError_t e = hipMemsetAsync(out, 0, sizeof(long long), st);
+    if (e != hipSuccess) return e;
+    k_sum_counts<<<stream_grid(n), kBlock, 0, st>>>(nnb, n,
+                                                   reinterpret_cast<unsigned long long*>(out));
     return hipGetLastError();
 }
 

@@ -133,7 +133,8 @@ def test_c4_fp64_1e14_and_mixed_1e12(torch_dev, oracle_mod):
 @pytest.mark.timeout(300)
 def test_c1_bench_workload(torch_dev, oracle_mod):
     """The benchmarked workload (N = 10^6 jittered lattice, h/sigma = 0.8) in the
-    benchmark's launch configuration: setup on the device, the preconditioner
+    benchmark's launch configuration: neighbour counts and their total against
+    the oracle, setup on the device, the preconditioner
     built with two factorisation batches in flight, the solve to 1e-12, for
     FP64 and mixed precision.  Judged by the true residual from the GPU matvec,
     that matvec against the oracle on 2000 sampled rows, the centre rows Z_c of
@@ -156,6 +157,13 @@ def test_c1_bench_workload(torch_dev, oracle_mod):
     P = oracle_mod.Problem(pts, w.sigma, w.cutoff, w.overlap)
     h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, st)
     try:
+        # neighbour counts and their total (the interactions per product that
+        # the benchmark's rate counts), bit-exact against the oracle
+        nnb, tot = R.rbf_neighbor_counts(h, w.n)
+        _, o_nnb = P.matvec(np.ones(w.n), with_counts=True)
+        assert np.array_equal(nnb, o_nnb)
+        assert tot == int(o_nnb.astype(np.int64).sum())
+        say("c1 interactions per product", tot)
         _, (ncx, ncy) = R.rbf_grid(h)
         ncells = ncx * ncy
         cells = sorted(c for c in {0, ncx + 1, 8191, 8192, 16383, 16384, ncells // 2, ncells - 1}
