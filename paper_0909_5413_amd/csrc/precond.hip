@@ -91,7 +91,7 @@ __device__ __forceinline__ int member_index(const int* rb, const int* re, int nr
 // slot) keeps its n_p x n_p lower triangle in a scratch slot, stored by
 // 32-row block rows (see roff).  The left-looking blocked Cholesky advances one
 // 64-column block column J at a time for every slot together, one launch per
-// J: each workgroup takes a 128-row tile below the diagonal block, updates it
+// J: each workgroup takes a 64-row tile below the diagonal block, updates it
 // with the finished block columns as MFMA tiles (accumulators in registers),
 // solves x L_JJ^T = a for its rows in two 32-column halves (substitution, one
 // row per thread, the diagonal blocks broadcast from LDS; the coupling block on
@@ -168,10 +168,15 @@ constexpr int kW2 = kT2 / 64;
 constexpr int kFB = 2 * kNB;    // columns of a factorisation block column; n_p is a multiple
 constexpr int kTS = 256;        // threads of a factorisation step (4 waves)
 constexpr int kWS = kTS / 64;
-constexpr int kRows = 128;      // rows per step tile
+// Rows per step tile: one 16-row MFMA tile per wave.  Small tiles keep the
+// step kernel near 128 registers, so four workgroups share a CU (its LDS is
+// the limit) and cover each other's latency.
+constexpr int kRows = 64;
 static_assert(kRows <= kTS, "the substitution gives one row to each thread");
-static_assert(kRows == 2 * 16 * kWS, "two row tiles per wave in a full tile");
-constexpr int kXS = kRows + 1;  // padded LDS row of a staged tile (conflict-free MFMA stores)
+static_assert(kRows == 16 * kWS, "one row tile per wave");
+// LDS row of a step tile's column: odd (conflict-free MFMA stores), and long
+// enough for the update's two staged chunks, which borrow the tile buffer
+constexpr int kXS = 81;
 constexpr int kTileGroup = 16;  // slots whose step tiles are interleaved on an XCD
 constexpr int kTri = kNB * (kNB + 1) / 2;
 constexpr int kLtElems = 2 * kNB * kNB;   // per slot: both diagonal 32x32 blocks of L_JJ
@@ -807,11 +812,11 @@ __device__ __forceinline__ void step_tile(T* __restrict__ A, const T* __restrict
 }
 
 // Block column J (64 columns): the launch has nslots_pad x tiles workgroups,
-// one per (slot, 128-row tile below the slot's diagonal block), ordered as
+// one per (slot, 64-row tile below the slot's diagonal block), ordered as
 // below.  lt_in: per slot, the diagonal 32x32 blocks of L_JJ transposed with
 // reciprocal pivots.
 template <typename T>
-__global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int nslots_pad,
+__global__ __launch_bounds__(kTS, 3) void k_chol_step(PrecondArgs a, int J, int nslots_pad,
                                                       T* __restrict__ scratch,
                                                       const int4* __restrict__ meta,
                                                       const T* __restrict__ lt_in) {
@@ -852,10 +857,7 @@ __global__ __launch_bounds__(kTS, 2) void k_chol_step(PrecondArgs a, int J, int 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double2* xy = a.xy + (size_t)slot * a.np_max;
     const int p = np - m.y;
-    if (np - R >= kRows)
-        step_tile<T, 2>(A, lt, xy, np, p, a.mk, a.norm, J, k0, R, wave, s);
-    else
-        step_tile<T, 1>(A, lt, xy, np, p, a.mk, a.norm, J, k0, R, wave, s);
+    step_tile<T, 1>(A, lt, xy, np, p, a.mk, a.norm, J, k0, R, wave, s);
 }
 
 // Diagonal block J0 > 0 of every slot, one workgroup of two waves per slot:
