@@ -79,7 +79,10 @@ typedef struct {
     int outer_iterations;   /* refinement steps (RBF_MIXED), else 0 */
     int restarts;           /* GMRES cycles completed */
     double rel_residual;    /* final true relative residual, FP64 */
-    /* phase seconds, named after the paper's time breakdown (Section 4.2) */
+    /* phase seconds, named after the paper's time breakdown (Section 4.2):
+       t_init is the handle's set-up (binning, sorting, neighbour lists; the
+       same figure for every solve on one handle), t_pcsetup the local
+       factorisations this call made (0 if they were already built) */
     double t_init, t_pcsetup, t_matmult, t_matsolve, t_vecmdot, t_other;
     long long interactions_per_matvec;  /* in-cutoff ordered pairs, i = j included;
                                            -1 until rbf_neighbor_counts has run */
@@ -89,6 +92,8 @@ typedef struct {
     size_t device_bytes;    /* bytes the handle holds on the device */
     int history_len;        /* entries in history (valid until the next call) */
     const double* history;  /* true relative residual at each cycle start and end */
+    int shifted_blocks;     /* RBF_MIXED: local blocks factored with a diagonal
+                               shift (FP32 Cholesky breakdown), else 0 */
 } rbf_solve_info;
 
 /* Set opts to the defaults listed above. */

@@ -61,7 +61,8 @@ class SolveInfo(C.Structure):
                 ("interactions_per_matvec", C.c_longlong), ("matvecs64", C.c_int),
                 ("matvecs32", C.c_int), ("precond_applies", C.c_int),
                 ("device_bytes", C.c_size_t),
-                ("history_len", C.c_int), ("history", C.POINTER(C.c_double))]
+                ("history_len", C.c_int), ("history", C.POINTER(C.c_double)),
+                ("shifted_blocks", C.c_int)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history"}

@@ -239,6 +239,7 @@ struct rbf_problem {
     float *xr = nullptr, *yr = nullptr;
     int *perm = nullptr, *cell_of = nullptr, *cell_start = nullptr;
     bool have_values = false;
+    double t_init = 0;                 // seconds of the handle's set-up
     double sc32 = 0;                   // FP32 coordinate scale
     long long interactions = -1;
     double* etab = nullptr;            // e^{-n/128}, n < ntab (device), or NULL
@@ -658,6 +659,7 @@ rbf_status create(const double* pts, const double* vals, bool on_device, long lo
     p->cutoff = cutoff;
     p->overlap = overlap;
     rbf_status s;
+    Timer t_init;
     if (on_device) {
         s = setup_impl(p, pts, vals, st);
     } else {
@@ -680,6 +682,7 @@ rbf_status create(const double* pts, const double* vals, bool on_device, long lo
         return s;
     }
     p->mark(st);
+    p->t_init = t_init.sec();   // setup_impl ends with a wait for its stream
     *out = p;
     return RBF_OK;
 }
@@ -1221,7 +1224,7 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
         info->outer_iterations = outer;
         info->restarts = cycles;
         info->rel_residual = rel;
-        info->t_init = 0;
+        info->t_init = p->t_init;
         info->t_pcsetup = t_pc;
         info->t_matmult = pt.matmult;
         info->t_matsolve = pt.matsolve;
@@ -1235,6 +1238,7 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
         info->device_bytes = p->bytes;
         info->history_len = (int)p->history.size();
         info->history = p->history.data();
+        info->shifted_blocks = opts.precision == RBF_MIXED ? p->shifted_blocks32 : 0;
     }
     return status;
 }

@@ -68,9 +68,11 @@ __device__ __forceinline__ double exp_neg_tab(double x, const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// exp(x) for -700 < x <= 0 from a 32-entry table T[j] = 2^(j/32) (correctly
-// rounded, held in LDS by the caller; 256 bytes, so lanes never conflict on
-// a bank): with k = rint(32 x / ln2) = 32 n + j (0 <= j < 32) and
+// exp(x) for -700 < x <= 0 by Tang's table-driven method (P. T. P. Tang,
+// "Table-driven implementation of the exponential function in IEEE
+// floating-point arithmetic", ACM TOMS 15(2), 1989) with a 32-entry table
+// T[j] = 2^(j/32) (correctly rounded, held in LDS by the caller; 256 bytes, so
+// lanes never conflict on a bank): with k = rint(32 x / ln2) = 32 n + j (0 <= j < 32) and
 // r = x - k ln2 / 32 (|r| <= ln2/64, ln2/32 split exactly as above),
 // exp(x) = 2^n T[j] exp(r), exp(r) by its degree-6 Taylor polynomial
 // (truncation below r^7/7! < 3.5e-18).
@@ -97,7 +99,8 @@ __device__ __forceinline__ double exp_neg_t32(double x, const double* T) {
 
 // ---------------------------------------------------------------------------
 // 2^(y/32) for y = d2 * beta <= 0, where beta folds the Gaussian's -1/(2 sigma^2)
-// and 32/ln2 (so 2^(y/32) = exp(-d2 / (2 sigma^2))), from a 32-entry table
+// and 32/ln2 (so 2^(y/32) = exp(-d2 / (2 sigma^2))), by Tang's table-driven
+// method (ACM TOMS 15(2), 1989) from a 32-entry table
 // T[j] = 2^(j/32) (correctly rounded, in LDS, as for exp_neg_t32).
 // k = rint(y) = 32 n + j is read from the fused product against the 1.5*2^52
 // shift; f = y - k comes from a second fused multiply-add of the same exact

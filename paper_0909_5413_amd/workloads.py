@@ -99,6 +99,35 @@ def staggered_lattice(n_side: int, lo: float = -1.0, hi: float = 1.0) -> np.ndar
     return np.ascontiguousarray(np.stack([xx.ravel(), yy.ravel()], axis=1))
 
 
+def evaluation_targets(pts: np.ndarray, cutoff: float, seed: int = 41):
+    """Targets for the interpolant off the nodes, and how many of them (the
+    last ones) lie farther than the cutoff from every node: five nodes, 60
+    points midway between consecutive nodes, 80 uniform points in the nodes'
+    bounding box, points 0.3 and 0.9 cutoffs outside each edge and corner of
+    that box (3 per side or corner and distance, 48 in all), and 4 points
+    more than a cutoff away from the box."""
+    rng = np.random.default_rng(seed)
+    lo, hi = pts.min(axis=0), pts.max(axis=0)
+    mid = 0.5 * (lo + hi)
+    out = [pts[:5], 0.5 * (pts[:60] + pts[1:61]), rng.uniform(lo, hi, (80, 2))]
+    near = []
+    for d in (0.3, 0.9):
+        for sx in (-1, 0, 1):
+            for sy in (-1, 0, 1):
+                if sx == 0 and sy == 0:
+                    continue
+                for t in (0.1, 0.5, 0.85):
+                    base = lo + t * (hi - lo)
+                    x = lo[0] - d * cutoff if sx < 0 else hi[0] + d * cutoff if sx > 0 else base[0]
+                    y = lo[1] - d * cutoff if sy < 0 else hi[1] + d * cutoff if sy > 0 else base[1]
+                    near.append((x, y))
+    out.append(np.array(near))
+    far = np.array([(hi[0] + 1.5 * cutoff, mid[1]), (lo[0] - 2.0 * cutoff, lo[1] - 2.0 * cutoff),
+                    (mid[0], hi[1] + 1.01 * cutoff), (50.0, -40.0)])
+    out.append(far)
+    return np.ascontiguousarray(np.concatenate(out)), len(far)
+
+
 # The workloads, sized like the paper's lattice runs (Sections 3 and 4).
 MINI = Workload("mini", 44, 0.8, rtol=1e-10, seed=SEED_BASE + 100,
                 notes="44x44 lattice, N=1936: small enough for dense checks")

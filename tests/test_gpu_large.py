@@ -74,9 +74,10 @@ def test_c2_fp64_and_mixed(torch_dev, oracle_mod, name):
         say(name, "precision", prec, "N", w.n)
         lam, y, info, st = solve(torch, w, d_pts, d_f, prec, 1e-12)
         assert st == R.RBF_OK, info.as_dict()
-        assert info.rel_residual <= 1.05e-12, info.as_dict()
-        # the GPU's own residual check, recomputed here from its matvec
-        assert np.linalg.norm(f - y) / np.linalg.norm(f) <= 1.05e-12
+        assert info.rel_residual <= 1e-12, info.as_dict()
+        # the GPU's own residual check, recomputed here from its matvec: two
+        # evaluations of one 2-norm agree to N u relative
+        assert np.linalg.norm(f - y) / np.linalg.norm(f) <= 1e-12 * (1 + w.n * 2.0 ** -53)
         err, res = sampled_rows(oracle_mod, pts, w, lam, y, f, 2000, 11 + prec)
         say(name, prec, "sampled matvec error / bar", err, "sampled residual", res)
         assert err <= 1e-13, err
@@ -122,8 +123,8 @@ def test_c4_fp64_1e14_and_mixed_1e12(torch_dev, oracle_mod):
         lam, y, info, st = solve(torch, w, d_pts, d_f, prec, rtol)
         say("c4", prec, info.as_dict()["iterations"], info.rel_residual)
         assert st == R.RBF_OK, info.as_dict()
-        assert info.rel_residual <= 1.05 * rtol, info.as_dict()
-        assert np.linalg.norm(f - y) / np.linalg.norm(f) <= 1.05 * rtol
+        assert info.rel_residual <= rtol, info.as_dict()
+        assert np.linalg.norm(f - y) / np.linalg.norm(f) <= rtol * (1 + w.n * 2.0 ** -53)
         err, res = sampled_rows(oracle_mod, pts, w, lam, y, f, 1000, 41 + prec)
         say("c4", prec, "sampled matvec error / bar", err, "sampled residual", res)
         assert err <= 1e-13, err
@@ -181,8 +182,8 @@ def test_c1_bench_workload(torch_dev, oracle_mod):
             torch.cuda.synchronize()
             lam_h, y_h, z_h = lam.cpu().numpy(), y.cpu().numpy(), d_z.cpu().numpy()
             assert status == R.RBF_OK, info.as_dict()
-            assert info.rel_residual <= 1.05e-12, info.as_dict()
-            assert np.linalg.norm(f - y_h) / np.linalg.norm(f) <= 1.05e-12
+            assert info.rel_residual <= 1e-12, info.as_dict()
+            assert np.linalg.norm(f - y_h) / np.linalg.norm(f) <= 1e-12 * (1 + w.n * 2.0 ** -53)
             err, res = sampled_rows(oracle_mod, pts, w, lam_h, y_h, f, 2000, 21 + prec)
             say("c1", prec, "iterations", info.iterations, "sampled matvec error / bar", err)
             assert err <= 1e-13, err

@@ -12,6 +12,7 @@ import pytest
 
 import paper_0909_5413_amd as R
 from paper_0909_5413_amd import workloads as W
+from tests.gates import residual_gate
 
 pytestmark = pytest.mark.gpu
 
@@ -158,6 +159,65 @@ def test_rasm_apply_parity(torch_dev, problems, name):
     assert rel <= 1e-7, rel
 
 
+@pytest.mark.parametrize("name", ["ragged", "mini"])
+def test_rasm_apply_elementwise(torch_dev, problems, name):
+    """Element by element against the oracle's RASM (eq. rasm: forward and back
+    substitution with the local Cholesky factor, centre rows kept).  Both sides
+    solve the same local systems backward-stably, so each centre value z_i of
+    cell c differs by at most about n_c kappa_c u (|A_c^-1| |v_c|)_i, with
+    kappa_c the local condition number (about 3e3 on the ragged h/sigma = 1.0
+    case, 1e6 at h/sigma = 0.8) and n_c the block size; the bar takes
+    10 n_c kappa_c u with |A_c^-1| from numpy's inverse of each block."""
+    say("rasm64 elementwise", name)
+    h, P, pts, f, sigma, cutoff = problems[name]
+    from tests import bruteforce as bf
+    P.rasm_setup()
+    v = W.random_weights(pts.shape[0], 17)
+    dv = torch_dev.tensor(v, device="cuda", dtype=torch_dev.float64)
+    dz = torch_dev.empty_like(dv)
+    R.rbf_precond_apply_device(h, dv, dz, R.RBF_FP64, R.RBF_ORDER_ORIGINAL,
+                               torch_dev.cuda.current_stream())
+    torch_dev.cuda.synchronize()
+    z = dz.cpu().numpy()
+    zo = P.rasm_apply(v)
+    u = np.finfo(float).eps / 2
+    worst = 0.0
+    for cell in range(P.ncells):
+        mem, kc, _ = P.rasm_block(cell, with_factor=False)
+        if kc == 0:
+            continue
+        A = bf.dense_matrix(pts[mem], sigma, None)
+        inv = np.linalg.inv(A)
+        ev = np.linalg.eigvalsh(A)
+        kappa = ev[-1] / ev[0]
+        own = mem[len(mem) - kc:]
+        scale = (np.abs(inv) @ np.abs(v[mem]))[len(mem) - kc:]
+        bar = 10 * len(mem) * kappa * u * scale
+        err = np.abs(z[own] - zo[own])
+        worst = max(worst, float((err / bar).max()))
+        assert np.all(err <= bar), (cell, float((err / bar).max()), kappa)
+    say("rasm64 elementwise worst error / bar", name, worst)
+
+
+@pytest.mark.parametrize("name", ["mini", "ragged"])
+def test_evaluate_off_nodes(problems, name):
+    """The interpolant (eq. rbf1) at targets off the nodes: between nodes,
+    scattered in the box, outside the nodes' bounding box (the target's cell
+    is clamped to the border cells) and farther than the cutoff from every
+    node (exactly zero), against the oracle's evaluation of the same weights,
+    element by element within 1e-13 of sum_j |lam_j| phi(|t - x_j|)."""
+    say("evaluate off nodes", name)
+    h, P, pts, f, sigma, cutoff = problems[name]
+    lam, info, st = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-10))
+    tg, nfar = W.evaluation_targets(pts, cutoff)
+    s = R.rbf_evaluate(h, tg)
+    so = P.evaluate(lam, tg)
+    scale = P.evaluate(np.abs(lam), tg)
+    err = np.abs(s - so)
+    assert np.all(err <= 1e-13 * scale), float(np.max(err / np.where(scale > 0, scale, 1)))
+    assert np.all(s[-nfar:] == 0.0) and np.all(so[-nfar:] == 0.0)
+
+
 @pytest.mark.parametrize("name", ["mini", "ragged", "ill"])
 def test_centre_rows_are_inverse_rows(problems, name):
     """Z_c is a backward-stable set of rows of A_c^{-1}: with A_c rebuilt in numpy,
@@ -216,7 +276,8 @@ def test_solve_fp64(problems, name, rtol):
     o = R.default_opts(rtol=rtol)
     lam, info, st = R.rbf_solve(h, pts.shape[0], o)
     res = P.rel_residual(f, lam)
-    assert res <= rtol * 1.05, (res, info.as_dict())
+    assert info.rel_residual <= rtol
+    assert res <= residual_gate(P, f, lam, rtol), (res, info.as_dict())
     _, oinfo = P.gmres(f, 30, rtol)
     assert abs(info.iterations - oinfo.iterations) <= 2, (info.iterations, oinfo.iterations)
     # evaluate at the nodes reproduces the data, and matches the oracle
@@ -230,14 +291,49 @@ def test_solve_fp64(problems, name, rtol):
 @pytest.mark.parametrize("name", ["mini", "c0"])
 def test_solve_mixed(problems, name):
     say("solve_mixed", name)
-    h, P, pts, f, *_ = problems[name]
+    h, P, pts, f, sigma, cutoff = problems[name]
     o = R.default_opts(rtol=1e-12, precision=R.RBF_MIXED)
     lam, info, st = R.rbf_solve(h, pts.shape[0], o)
     res = P.rel_residual(f, lam)
-    assert res <= 1.05e-12, (res, info.as_dict())
-    xo, _ = P.gmres(f, 30, 1e-12)
+    assert info.rel_residual <= 1e-12
+    assert res <= residual_gate(P, f, lam, 1e-12), (res, info.as_dict())
+    xo, oinfo = P.gmres(f, 30, 1e-12)
     werr = np.linalg.norm(lam - xo) / np.linalg.norm(xo)
-    say("mixed weight error vs oracle", name, werr, "outer", info.outer_iterations)
+    # two weight vectors that both meet the residual test agree only to the
+    # conditioning of A: ||lam - xo|| <= ||A^-1|| ||A (lam - xo)|| and
+    # ||A (lam - xo)|| <= (res + res_oracle) ||f||, with ||xo|| >= ||f|| / ||A||
+    stag = W.staggered_lattice(int(round(np.sqrt(pts.shape[0]))))
+    s_mixed = R.rbf_evaluate(h, stag)
+    s_or = P.evaluate(xo, stag)
+    ierr = np.abs(s_mixed - s_or).max() / np.abs(f).max()
+    say("mixed vs oracle", name, "weights", werr, "interpolant", ierr,
+        "outer", info.outer_iterations)
+    if name == "mini":
+        from tests import bruteforce as bf
+        ev = np.linalg.eigvalsh(bf.dense_matrix(pts, sigma, cutoff))
+        kappa = ev[-1] / ev[0]
+        bound = kappa * (res + oinfo.rel_residual)
+        say("mixed weight error bound kappa (res + res_oracle)", kappa, bound)
+        assert werr <= bound, (werr, bound)
+    # the interpolants differ by A(lam - xo) at the nodes and its smooth
+    # continuation between them: far below the interpolation error itself
+    assert ierr <= 1e-8, ierr
+
+
+def test_mixed_shifted_blocks(problems):
+    """The FP32 factorisation of the h/sigma = 0.6 blocks (condition numbers
+    ~1e15, far beyond FP32) needs diagonal shifts on some blocks; the FP64 one
+    never shifts; the mixed solve still meets its FP64 residual."""
+    say("shifted blocks")
+    h, P, pts, f, *_ = problems["ill"]
+    _, i64, _ = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-10),
+                            ok=(R.RBF_OK, R.RBF_ENOCONV))
+    lam, i32, st = R.rbf_solve(h, pts.shape[0],
+                               R.default_opts(rtol=1e-10, precision=R.RBF_MIXED, max_iters=600),
+                               ok=(R.RBF_OK, R.RBF_ENOCONV))
+    say("shifted blocks", i32.shifted_blocks, "of", P.ncells, R.status_name(st))
+    assert i64.shifted_blocks == 0
+    assert i32.shifted_blocks > 0
 
 
 def test_determinism(torch_dev, problems):
@@ -263,7 +359,7 @@ def test_order_invariance(problems):
         R.rbf_destroy(h2)
     lam = np.empty_like(lam2)
     lam[p] = lam2
-    assert P.rel_residual(f, lam) <= 1.05e-12
+    assert P.rel_residual(f, lam) <= residual_gate(P, f, lam, 1e-12)
 
 
 def test_error_codes(torch_dev):

@@ -14,8 +14,10 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import paper_0909_5413_amd as R
 from paper_0909_5413_amd import workloads as W
+from tests.gates import residual_gate
 
 pytestmark = pytest.mark.gpu
 
@@ -52,6 +54,21 @@ def alone(w, pts, f, prec):
     return lam, st
 
 
+def oracle_judges(w, pts, f, lam, st):
+    """A served request that reports convergence meets its tolerance by the
+    oracle's own FP64 residual (Section 2.1's system, truncated matrix)."""
+    if st != R.RBF_OK:
+        return
+    P = oracle.Problem(pts, w.sigma, w.cutoff, w.overlap)
+    try:
+        res = P.rel_residual(f, lam)
+        gate = residual_gate(P, f, lam, w.rtol)
+    finally:
+        P.close()
+    say("oracle residual", w.name, res, "gate", gate)
+    assert res <= gate, (w.name, res, gate)
+
+
 def test_mix_equals_alone(torch_dev):
     reqs = mix(8, 777000)
     ref = []
@@ -68,6 +85,7 @@ def test_mix_equals_alone(torch_dev):
             say("mixed-in", w.name, R.status_name(st), res.latency, res.info.iterations)
             assert st == st0
             assert np.array_equal(lam, lam0)
+            oracle_judges(w, pts, f, lam, st)
         stats = R.rbf_server_stats(srv)
         assert stats["finished"] == len(reqs) and stats["active"] == 0
         assert stats["bytes_charged"] == 0
@@ -115,6 +133,7 @@ def test_admission_budget_and_failures(torch_dev):
                 assert st == R.RBF_OK
                 lam0, st0 = alone(w, pts, f, prec)
                 assert np.array_equal(lam, lam0)
+                oracle_judges(w, pts, f, lam, st)
         assert R.rbf_server_stats(srv)["bytes_charged"] == 0
     finally:
         R.rbf_server_destroy(srv)

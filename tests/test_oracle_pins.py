@@ -287,3 +287,84 @@ def test_error_codes(oracle_mod):
     P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
     _, info = P.gmres(w.values(pts), 30, 1e-30, max_iters=5, raise_on_error=False)
     assert info.status == 6 and info.iterations == 5
+
+
+# ------------------------------------------------------------- true residual
+def test_rel_residual_matches_dense(oracle_mod):
+    """||f - A x||_2 / ||f||_2 with A the truncated matrix (the stop test of the
+    solve, Section 2.1's system) against the dense truncated matrix built by
+    brute force: x = 0 gives exactly 1; random x, a solution-like x and
+    f = 0 (absolute norm then) agree with the dense value to the rounding of
+    the products, 1e-14 of (|| |A||x| || + ||f||) / ||f||."""
+    w, pts = lattice(44, 0.8)
+    f = w.values(pts)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    A = bf.dense_matrix(pts, w.sigma, w.cutoff)
+    assert P.rel_residual(f, np.zeros(w.n)) == 1.0
+    xs = [W.random_weights(w.n, 31), 1e3 * W.random_weights(w.n, 32),
+          np.linalg.solve(A, f), np.linalg.solve(A, f) * (1 + 1e-6)]
+    for x in xs:
+        ref = np.linalg.norm(f - A @ x) / np.linalg.norm(f)
+        slack = 1e-14 * (np.linalg.norm(np.abs(A) @ np.abs(x)) + np.linalg.norm(f))
+        got = P.rel_residual(f, x)
+        assert abs(got - ref) <= slack / np.linalg.norm(f), (got, ref)
+    # the solution-like x really has a small residual, the perturbed one does not
+    assert P.rel_residual(f, xs[2]) < 1e-11 < P.rel_residual(f, xs[3])
+    # f = 0: the absolute norm ||A x||
+    x = W.random_weights(w.n, 33)
+    got = P.rel_residual(np.zeros(w.n), x)
+    ref = np.linalg.norm(A @ x)
+    assert abs(got - ref) <= 1e-14 * np.linalg.norm(np.abs(A) @ np.abs(x))
+
+
+# ------------------------------------------------------------------ evaluate
+def bruteforce_evaluate(pts, lam, targets, sigma, cutoff):
+    """s(t) = sum_j lam_j phi(|t - x_j|) over every node within the cutoff, and
+    the scale sum_j |lam_j| phi(|t - x_j|) over the same nodes."""
+    mask = bf.cutoff_mask(targets[:, 0], targets[:, 1], pts[:, 0], pts[:, 1], cutoff)
+    d2, _, _ = bf.pair_d2(targets[:, 0], targets[:, 1], pts[:, 0], pts[:, 1])
+    K = np.where(mask, bf.gaussian(d2, sigma), 0.0)
+    return K @ lam, K @ np.abs(lam), mask
+
+
+@pytest.mark.parametrize("n_side,ratio", [(44, 0.8), (31, 1.0)])
+def test_evaluate_matches_bruteforce(oracle_mod, n_side, ratio):
+    w, pts = lattice(n_side, ratio)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    lam = W.random_weights(w.n, 42)
+    tg, nfar = W.evaluation_targets(pts, w.cutoff)
+    s = P.evaluate(lam, tg)
+    ref, scale, mask = bruteforce_evaluate(pts, lam, tg, w.sigma, w.cutoff)
+    assert np.all(np.abs(s - ref) <= 1e-14 * scale)
+    # the off-grid targets within the cutoff do see nodes, and clamping to the
+    # border cell finds every one of them
+    near = slice(len(tg) - nfar - 48, len(tg) - nfar)
+    assert np.all(mask[near].sum(axis=1)[:24] > 0)
+    # farther than the cutoff from every node: exactly zero
+    assert not mask[-nfar:].any()
+    assert np.all(s[-nfar:] == 0.0)
+    # at the nodes the interpolant is the truncated product (A lam)_i
+    A = bf.dense_matrix(pts, w.sigma, w.cutoff)
+    assert np.all(np.abs(s[:5] - (A @ lam)[:5]) <= 1e-14 * (np.abs(A) @ np.abs(lam))[:5])
+
+
+def test_not_positive_definite(oracle_mod):
+    """h/sigma = 0.1 with one cell holding all points: the local Gaussian matrix
+    has numerical rank far below its size (condition ~ exp(pi^2 sigma^2/h^2)),
+    and the Cholesky factorisation meets a non-positive pivot."""
+    w, pts = lattice(30, 0.1)
+    P = oracle_mod.Problem(pts, w.sigma, 6 * w.sigma)
+    assert P.ncells == 1
+    with pytest.raises(oracle_mod.OracleError) as e:
+        P.rasm_setup()
+    assert e.value.code == 5
+    x, info = P.gmres(w.values(pts), 30, 1e-10, raise_on_error=False)
+    assert info.status == 5
+
+
+def test_nan_residual(oracle_mod):
+    """Finite data whose 2-norm overflows: the relative residual is Inf/Inf."""
+    w, pts = lattice(20, 0.8)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    _, info = P.gmres(np.full(w.n, 1e200), 30, 1e-10, raise_on_error=False)
+    assert info.status == 8
