@@ -190,6 +190,23 @@ rbf_status rbf_neighbor_counts(rbf_problem* p, int* nnb, long long* total);
 rbf_status rbf_matvec_device(rbf_problem* p, const double* d_w, double* d_y,
                              rbf_precision precision, rbf_order order, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the product
+ * of rbf_matvec_device in the caller's ORIGINAL order, with the sorted-order
+ * staging of w and y in a fixed device array that the library holds on every
+ * device it runs on (two vectors of RBF_NOALLOC_MAX_POINTS doubles, 64 MiB)
+ * instead of blocks it allocates.  The call allocates nothing and does not
+ * wait; it enqueues three kernels on `stream`.  d_w and d_y are n device
+ * doubles in original order (caller-owned; they may not overlap).  The array
+ * is shared by every call on one device and keeps the last call's contents:
+ * calls that overlap in time on one device (concurrent streams or threads)
+ * race on it and must be serialised by the caller.  Errors: RBF_EINVAL (NULL
+ * argument, bad precision), RBF_ELIMIT (more than RBF_NOALLOC_MAX_POINTS
+ * points), RBF_EDEVICE (the array's address could not be read). */
+#define RBF_NOALLOC_MAX_POINTS 4194304
+rbf_status rbf_matvec_device_noalloc(rbf_problem* p, const double* d_w, double* d_y,
+                                     rbf_precision precision, void* stream);
+
 /* z = M^{-1} v, RASM (Section 2.2, eq. rasm), on device vectors; builds the
  * preconditioner of that precision first if needed. */
 rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d_z,

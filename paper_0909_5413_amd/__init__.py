@@ -22,12 +22,14 @@ RBF_FP64, RBF_MIXED = 0, 1
 RBF_ORDER_ORIGINAL, RBF_ORDER_SORTED = 0, 1
 RBF_MAX_BLOCK = 1536
 RBF_MAX_CELL_POINTS = 1536
+RBF_NOALLOC_MAX_POINTS = 4194304
 
 EXPORTED = [
     "rbf_default_opts", "rbf_setup", "rbf_setup_device", "rbf_set_values",
     "rbf_precond_setup", "rbf_solve", "rbf_solve_device", "rbf_evaluate",
     "rbf_evaluate_device", "rbf_destroy", "rbf_block_cache", "rbf_grid", "rbf_binning",
-    "rbf_neighbor_counts", "rbf_matvec_device", "rbf_precond_apply_device",
+    "rbf_neighbor_counts", "rbf_matvec_device", "rbf_matvec_device_noalloc",
+    "rbf_precond_apply_device",
     "rbf_precond_block", "rbf_set_profiling", "rbf_set_graphs", "rbf_setup_kernel_times",
     "rbf_server_default_opts", "rbf_server_create", "rbf_server_submit", "rbf_server_wait",
     "rbf_server_stats", "rbf_server_destroy", "rbf_status_string", "rbf_last_error",
@@ -112,6 +114,7 @@ def lib():
         "rbf_binning": (C.c_int, [vp, vp, vp, vp]),
         "rbf_neighbor_counts": (C.c_int, [vp, vp, lp]),
         "rbf_matvec_device": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
+        "rbf_matvec_device_noalloc": (C.c_int, [vp, vp, vp, C.c_int, vp]),
         "rbf_precond_apply_device": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
         "rbf_precond_block": (C.c_int, [vp, C.c_longlong, C.c_int, vp, vp, ip, ip]),
         "rbf_set_profiling": (C.c_int, [vp, C.c_int]),
@@ -283,6 +286,11 @@ def rbf_matvec_device(h: int, d_w, d_y, precision: int = RBF_FP64,
                       order: int = RBF_ORDER_ORIGINAL, stream=None):
     _check(lib().rbf_matvec_device(h, _ptr(d_w), _ptr(d_y), precision, order, _stream(stream)),
            "rbf_matvec_device")
+
+
+def rbf_matvec_device_noalloc(h: int, d_w, d_y, precision: int = RBF_FP64, stream=None):
+    _check(lib().rbf_matvec_device_noalloc(h, _ptr(d_w), _ptr(d_y), precision, _stream(stream)),
+           "rbf_matvec_device_noalloc")
 
 
 def rbf_precond_apply_device(h: int, d_v, d_z, precision: int = RBF_FP64,

@@ -1526,6 +1526,29 @@ rbf_status rbf_matvec_device(rbf_problem* p, const double* d_w, double* d_y,
     }
 }
 
+rbf_status rbf_matvec_device_noalloc(rbf_problem* p, const double* d_w, double* d_y,
+                                     rbf_precision precision, void* stream) {
+    if (!p || !d_w || !d_y) return fail(RBF_EINVAL, "NULL argument");
+    if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_EINVAL, "bad precision");
+    if (p->n > rbf::kNoAllocMaxPoints)
+        return fail(RBF_ELIMIT, "rbf_matvec_device_noalloc serves at most %lld points (got %lld)",
+                    rbf::kNoAllocMaxPoints, p->n);
+    hipStream_t st = as_stream(stream);
+    MarkOnExit mk{p, st};
+    try {
+        double* scr = nullptr;
+        HIP_TRY(rbf::noalloc_scratch(p->device, &scr));
+        double* ws = scr;
+        double* ys = scr + rbf::kNoAllocMaxPoints;
+        HIP_TRY(rbf::launch_permute(d_w, p->perm, p->n, ws, st));
+        RBF_TRY(matvec(p, precision, ws, ys, st));
+        HIP_TRY(rbf::launch_unpermute(ys, p->perm, p->n, d_y, st));
+        return RBF_OK;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_matvec_device_noalloc");
+    }
+}
+
 rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d_z,
                                     rbf_precision precision, rbf_order order, void* stream) {
     if (!p || !d_v || !d_z) return fail(RBF_EINVAL, "NULL argument");

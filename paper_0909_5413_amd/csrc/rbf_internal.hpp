@@ -212,6 +212,13 @@ void set_setup_lanes(rbf_problem* p, int lanes);
 hipError_t cached_alloc(int dev, size_t bytes, void** out, size_t* got);
 void cached_free(int dev, void* p, size_t bytes, hipStream_t st);
 
+// ---- allocation-free entry point (noalloc.hip) -------------------------------
+// Points the fixed device scratch serves: two vectors of this many doubles.
+constexpr long long kNoAllocMaxPoints = 1LL << 22;
+// Device address of the scratch array on `device` (2 * kNoAllocMaxPoints
+// doubles), looked up with hipGetSymbolAddress on the first call per device.
+hipError_t noalloc_scratch(int device, double** out);
+
 // ---- Krylov vector operations (krylov.hip) -----------------------------------
 constexpr int kDotBlocks = 1024;
 // out[k] = <V_k, w> for k < nv (V column k at V + k*ldv), deterministic
