@@ -151,6 +151,79 @@ def event_time(torch, stream, fn, reps):
     return start.elapsed_time(end) / reps
 
 
+def event_median(torch, stream, fn, warmup, reps):
+    """Median milliseconds of fn() over reps launches, each bracketed by its
+    own HIP event pair on stream, after warmup untimed launches."""
+    import numpy as np
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    ev[-1][1].synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, B, D, precision, reps=3):
+    """Seconds from the resident points to weights at the workload's tolerance
+    with box subdomains (setup, geometry, local factorisations, solve): the
+    median of reps - 1 runs after one warm-up."""
+    import ctypes as C
+    import numpy as np
+    times, info, zbytes = [], None, 0.0
+    opts = R.default_opts(rtol=w.rtol, precision=precision, stream=stream, max_iters=2000)
+    for rep in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+        try:
+            R.rbf_set_geometry(h, B, D, stream)
+            R.rbf_precond_setup(h, precision, stream)
+            inf, st = R.rbf_solve_device(h, d_lam, opts, ok=(R.RBF_OK, R.RBF_ENOCONV))
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            info = inf.as_dict()
+            info["status"] = R.status_name(st)
+            if rep == 0:
+                nx = int(np.floor((float(d_pts[:, 0].max()) - float(d_pts[:, 0].min())) * (1.0 / B))) + 1
+                ny = int(np.floor((float(d_pts[:, 1].max()) - float(d_pts[:, 1].min())) * (1.0 / B))) + 1
+                no, nc = C.c_int(), C.c_int()
+                for b in range(nx * ny):
+                    R.lib().rbf_precond_block(h, b, precision, None, None, C.byref(no), C.byref(nc))
+                    zbytes += float(no.value) * nc.value
+        finally:
+            R.rbf_destroy(h)
+    s = 8.0 if precision == R.RBF_FP64 else 4.0
+    return {"s_to_tol": float(np.median(times[1:])), "status": info["status"],
+            "iterations": info["iterations"], "outer": info["outer_iterations"],
+            "rel_residual": info["rel_residual"], "t_pcsetup": info["t_pcsetup"],
+            "z_bytes": zbytes * s}
+
+
+def geometry_run(R, torch, w, d_pts, d_f, d_lam, stream, sweep):
+    """The paper's optimum B = 5 sigma, D = 1.9 B (Section 3.2) on the
+    workload, FP64 and mixed; with sweep, iterations and seconds over
+    B in {3, 4, 5, 6, 7} sigma and D in {1.5, 1.7, 1.9, 2.1, 2.3} B."""
+    out = {"B_over_sigma": 5.0, "D_over_B": 1.9}
+    B = 5.0 * w.sigma
+    for tag, prec in (("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED)):
+        out[tag] = geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, B, 1.9 * B, prec)
+        log("geometry", tag, out[tag])
+    if sweep:
+        rows = []
+        for Bs in (3.0, 4.0, 5.0, 6.0, 7.0):
+            for Dr in (1.5, 1.7, 1.9, 2.1, 2.3):
+                r = geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, Bs * w.sigma,
+                                   Dr * Bs * w.sigma, R.RBF_FP64, reps=2)
+                rows.append({"B_over_sigma": Bs, "D_over_B": Dr, **r})
+                log("sweep", rows[-1])
+        out["sweep_fp64"] = rows
+    return out
+
+
 def cpu_baseline(workload, n_side):
     import numpy as np
     import oracle
@@ -189,6 +262,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-geometry", action="store_true")
+    ap.add_argument("--sweep-geometry", action="store_true",
+                    help="also time B in {3..7} sigma x D/B in {1.5..2.3} (Figs. 6 and 7)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving stream to run (the configuration's 512)")
     ap.add_argument("--serve-active", type=int, default=8)
@@ -267,10 +343,14 @@ def main():
         kernels["precond_setup64"] = {
             "bound": "alu", "achieved": flops / (t_pc * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "ms": t_pc, "flops_per_launch": flops}
+        # the matvec microbenchmark: w ~ U(-1, 1) from seed 5413 + 11, five
+        # warm-up launches, the median of 50 launches each timed by its own
+        # event pair
         wv = torch.tensor(W.random_weights(w.n, W.SEED_BASE + 11), device=dev)
         yv = torch.empty_like(wv)
-        R.rbf_matvec_device(h, wv, yv, R.RBF_FP64, R.RBF_ORDER_SORTED, stream)
-        t_mv = event_time(torch, stream, lambda: R.rbf_matvec_device(
+        t_mv = event_median(torch, stream, lambda: R.rbf_matvec_device(
+            h, wv, yv, R.RBF_FP64, R.RBF_ORDER_SORTED, stream), 5, 50)
+        t_mv_b2b = event_time(torch, stream, lambda: R.rbf_matvec_device(
             h, wv, yv, R.RBF_FP64, R.RBF_ORDER_SORTED, stream), args.kernel_reps)
         rate = inter / (t_mv * 1e-3)
         # in the solve the matvec launches sit between the RASM applies and the
@@ -280,14 +360,15 @@ def main():
         kernels["matvec64"] = {
             "bound": "alu", "achieved": rate * OPS_PER_INTERACTION / 1e12,
             "peak": VALU_OPS_PER_S / 1e12, "unit": "TFLOP/s", "ms": t_mv,
-            "interactions_per_s": rate,
+            "interactions_per_s": rate, "timing": "median of 50 event-timed launches after 5",
+            "back_to_back_ms": t_mv_b2b,
+            "back_to_back_interactions_per_s": inter / (t_mv_b2b * 1e-3),
             "r64_interactions_per_s": VALU_OPS_PER_S / OPS_PER_INTERACTION,
             "in_solve_ms": ms_in_solve,
             "in_solve_interactions_per_s": inter / (ms_in_solve * 1e-3),
             "in_solve_frac_r64": inter / (ms_in_solve * 1e-3) * OPS_PER_INTERACTION / VALU_OPS_PER_S}
-        R.rbf_matvec_device(h, wv, yv, R.RBF_MIXED, R.RBF_ORDER_SORTED, stream)
-        t_mv32 = event_time(torch, stream, lambda: R.rbf_matvec_device(
-            h, wv, yv, R.RBF_MIXED, R.RBF_ORDER_SORTED, stream), args.kernel_reps)
+        t_mv32 = event_median(torch, stream, lambda: R.rbf_matvec_device(
+            h, wv, yv, R.RBF_MIXED, R.RBF_ORDER_SORTED, stream), 5, 50)
         kernels["matvec32"] = {"ms": t_mv32, "interactions_per_s": inter / (t_mv32 * 1e-3)}
         R.rbf_precond_apply_device(h, wv, yv, R.RBF_FP64, R.RBF_ORDER_SORTED, stream)
         t_ra = event_time(torch, stream, lambda: R.rbf_precond_apply_device(
@@ -368,6 +449,7 @@ def main():
         fmax = float(fex.abs().max())
         mixed = {"s_to_tol": tm, "status": R.status_name(mst),
                  "iterations_inner": minfo.iterations, "outer": minfo.outer_iterations,
+                 "shifted_blocks": minfo.shifted_blocks,
                  "rel_residual": minfo.rel_residual, "weight_rel_diff_vs_fp64": werr,
                  "interpolant_points": int(tg.shape[0]),
                  "interp_err_fp64": float((s_64 - fex).abs().max()) / fmax,
@@ -375,6 +457,16 @@ def main():
                  "interp_rel_diff_mixed_vs_fp64": float((s_mx - s_64).abs().max() / s_64.abs().max()),
                  "evaluate_ms": t_ev, "evaluations_per_s": tg.shape[0] / (t_ev * 1e-3)}
         log("mixed", mixed)
+
+    # ---- the paper's subdomain geometry: boxes of side B, overlapping squares of
+    # side D (its measured optimum B = 5 sigma, D = 1.9 B) against the 3x3 cells
+    geometry = None
+    if not args.no_geometry:
+        geometry = geometry_run(R, torch, w, d_pts, d_f, d_lam, stream, args.sweep_geometry)
+        geometry["cells_3x3_fp64"] = {
+            "s_to_tol": ms_step / 1e3, "iterations": last["iterations"],
+            "z_bytes": float(np.sum(n_omega[n_c > 0].astype(np.float64) * n_c[n_c > 0])) * 8.0}
+        log("geometry", geometry)
 
     serving = None
     if not args.no_serve:
@@ -403,12 +495,13 @@ def main():
                    "n": w.n, "rtol": w.rtol, "interactions_per_matvec": inter},
         "s_to_tol_fp64": ms_step / 1e3,
         "fp64_solve": {k: last[k] for k in ("iterations", "restarts", "rel_residual",
-                                            "t_pcsetup", "t_matmult", "t_matsolve",
+                                            "t_init", "t_pcsetup", "t_matmult", "t_matsolve",
                                             "t_vecmdot", "t_other", "matvecs64",
                                             "precond_applies")},
         "mixed": mixed,
         "p99_latency_s": serving["fp64"]["latency_p99_s"] if serving else None,
         "serving": serving,
+        "geometry": geometry,
         "roofline": roofline,
         "kernels": kernels,
         "setup_kernels_ms": {k: {"ms": v[0], "launches": v[1]} for k, v in setup_k.items()},

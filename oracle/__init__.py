@@ -66,6 +66,8 @@ def lib():
                                 C.c_int]
         L.orc_rel_residual.argtypes = [vp, dp, dp, dp]
         L.orc_num_threads.argtypes = []
+        L.orc_set_geometry.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+        L.orc_subdomains.argtypes = [vp, lp]
         _lib = L
     return _lib
 
@@ -119,6 +121,18 @@ class Problem:
         self.x0, self.y0, self.L, self.invL = (float(v) for v in g)
         self.ncx, self.ncy = int(nc[0]), int(nc[1])
         self.ncells = self.ncx * self.ncy
+
+    def set_geometry(self, B: float, D: float, T: float = 0.0):
+        """Subdomain boxes of side B, overlapping squares of side D, matvec
+        truncation square of side T (0: the radial cutoff)."""
+        rc = lib().orc_set_geometry(self._h, float(B), float(D), float(T))
+        if rc:
+            raise OracleError(rc, "orc_set_geometry")
+
+    def subdomains(self):
+        nxy = np.zeros(2, dtype=np.int64)
+        lib().orc_subdomains(self._h, _lp(nxy))
+        return int(nxy[0]), int(nxy[1])
 
     def close(self):
         if getattr(self, "_h", None):

@@ -27,6 +27,11 @@
  *  - GMRES (Section 2.2, last paragraph; Saad's textbook), restarted, right
  *    preconditioned, modified Gram-Schmidt Arnoldi, Givens rotations for the
  *    small least-squares problem.
+ *  - The paper's parametric geometry (Section 3.1, Fig. 3), on request
+ *    (orc_set_geometry): non-overlapping subdomains are boxes of side B,
+ *    overlapping ones the squares of side D centred on them, and optionally
+ *    the matvec of a target keeps only the sources in the square of side T
+ *    centred on its box.
  *
  * Readings where the paper does not fix a detail (each applied identically by
  * the GPU library):
@@ -36,7 +41,11 @@
  *  - a pair is in the cutoff iff fma(dx, dx, dy*dy) <= r_c*r_c, i = j included;
  *  - local matrices use the untruncated Gaussian (always SPD for distinct
  *    points), ordered neighbour cells by (dy, dx) ascending, the centre last;
- *  - stop on the true relative residual ||f - A x|| / ||f|| <= rtol.
+ *  - stop on the true relative residual ||f - A x|| / ||f|| <= rtol;
+ *  - boxes: index floor((x - x0) * (1/B)) clamped, centre x0 + (b + 1/2) B,
+ *    a point is in a square of side S around a centre iff |x - c| <= S/2
+ *    along both axes; a box's members are its own points and the points of
+ *    its D-square, the others first, each part in sorted order.
  */
 #include "rbf_oracle.h"
 
@@ -52,6 +61,12 @@ struct orc_problem {
     long long n;
     double sigma, cutoff;
     int overlap;
+    /* subdomain geometry in lengths (Section 3.1, Fig. 3), geo = 1 once set:
+     * boxes of side B on a grid anchored at (x0, y0), overlapping squares of
+     * side D, truncation square of side T (T = 0: the radial cutoff) */
+    int geo;
+    double B, D, T, invB;
+    long long nbx, nby;
     /* grid */
     double x0, y0, L, invL;
     long long ncx, ncy, ncells;
@@ -230,10 +245,65 @@ int orc_binning(const orc_problem* p, int* cell_of, int* perm, long long* cell_s
 
 /* ---- truncated matvec (Section 2.3) ------------------------------------------ */
 
+/* ---- subdomain boxes (Section 3.1, Fig. 3) ---------------------------------- */
+
+/* box of a point: the cell rule with side B, clamped to the box grid */
+static long long box_index(const orc_problem* p, double x, double y, long long* bx, long long* by) {
+    *bx = cell_coord(x, p->x0, p->invB, p->nbx);
+    *by = cell_coord(y, p->y0, p->invB, p->nby);
+    return (*by) * p->nbx + (*bx);
+}
+
+/* centre of box (bx, by) */
+static void box_centre(const orc_problem* p, long long bx, long long by, double* cx, double* cy) {
+    *cx = p->x0 + ((double)bx + 0.5) * p->B;
+    *cy = p->y0 + ((double)by + 0.5) * p->B;
+}
+
+/* the cells that hold every point of the square [cx - h, cx + h] x [cy - h, cy + h]:
+ * the cells of its corners, widened by one (rounding at the edges), clamped */
+static void cells_of_square(const orc_problem* p, double cx, double cy, double h, long long* xa,
+                            long long* xb, long long* ya, long long* yb) {
+    *xa = cell_coord(cx - h, p->x0, p->invL, p->ncx) - 1;
+    *xb = cell_coord(cx + h, p->x0, p->invL, p->ncx) + 1;
+    *ya = cell_coord(cy - h, p->y0, p->invL, p->ncy) - 1;
+    *yb = cell_coord(cy + h, p->y0, p->invL, p->ncy) + 1;
+    if (*xa < 0) *xa = 0;
+    if (*ya < 0) *ya = 0;
+    if (*xb > p->ncx - 1) *xb = p->ncx - 1;
+    if (*yb > p->ncy - 1) *yb = p->ncy - 1;
+}
+
+/* box truncation of the matvec (Section 3.1): the sources in the square of
+ * side T centred on the target's box, in cell order then sorted order */
+static double box_sum(const orc_problem* p, double x, double y, const double* wsorted, int* count) {
+    long long bx, by, xa, xb, ya, yb;
+    double cx, cy;
+    box_index(p, x, y, &bx, &by);
+    box_centre(p, bx, by, &cx, &cy);
+    const double h = 0.5 * p->T;
+    cells_of_square(p, cx, cy, h, &xa, &xb, &ya, &yb);
+    double s = 0.0;
+    int cnt = 0;
+    for (long long ny = ya; ny <= yb; ++ny)
+        for (long long nx = xa; nx <= xb; ++nx) {
+            long long c = ny * p->ncx + nx;
+            for (long long j = p->cell_start[c]; j < p->cell_start[c + 1]; ++j)
+                if (fabs(p->xs[j] - cx) <= h && fabs(p->ys[j] - cy) <= h) {
+                    s += wsorted[j] * phi_of_d2(dist2(x, y, p->xs[j], p->ys[j]), p->sigma);
+                    ++cnt;
+                }
+        }
+    if (count) *count = cnt;
+    return s;
+}
+
 /* sum over the sources of the 3x3 block of cells around (cx, cy), in (dy, dx)
- * order then sorted order, of wsorted_j * phi for pairs within the cutoff. */
+ * order then sorted order, of wsorted_j * phi for pairs within the cutoff
+ * (or, with a truncation square T set, over the sources in that square). */
 static double cell_sum(const orc_problem* p, double x, double y, long long cx, long long cy,
                        const double* wsorted, int* count) {
+    if (p->geo && p->T > 0.0) return box_sum(p, x, y, wsorted, count);
     double rc2 = p->cutoff * p->cutoff;
     double s = 0.0;
     int cnt = 0;
@@ -298,10 +368,39 @@ int orc_evaluate(const orc_problem* p, const double* lambda, const double* targe
 
 /* ---- RASM (Section 2.2, eq. rasm) ------------------------------------------- */
 
+/* members of the overlapping subdomain of box b (geometry set): the points
+ * of the square of side D centred on the box, in sorted order, with the box's
+ * own points moved last (still in sorted order). */
+static int box_members(const orc_problem* p, long long b, long long* sorted_idx, int* ncentre) {
+    long long bx = b % p->nbx, by = b / p->nbx, xa, xb, ya, yb, ox, oy;
+    double cx, cy;
+    box_centre(p, bx, by, &cx, &cy);
+    const double h = 0.5 * p->D;
+    cells_of_square(p, cx, cy, h, &xa, &xb, &ya, &yb);
+    int k = 0, kc = 0;
+    for (int own = 0; own <= 1; ++own)
+        for (long long ny = ya; ny <= yb; ++ny)
+            for (long long nx = xa; nx <= xb; ++nx) {
+                long long c = ny * p->ncx + nx;
+                for (long long j = p->cell_start[c]; j < p->cell_start[c + 1]; ++j) {
+                    const int mine = box_index(p, p->xs[j], p->ys[j], &ox, &oy) == b;
+                    const int inside = fabs(p->xs[j] - cx) <= h && fabs(p->ys[j] - cy) <= h;
+                    if (own ? mine : (inside && !mine)) {
+                        if (sorted_idx) sorted_idx[k] = j;
+                        ++k;
+                        kc += own;
+                    }
+                }
+            }
+    if (ncentre) *ncentre = kc;
+    return k;
+}
+
 /* members of the overlapping subdomain of cell c, as sorted-order indices:
  * neighbour cells in (dy, dx) ascending order, then the cell itself. */
 static int block_members(const orc_problem* p, long long c, long long* sorted_idx,
                          int* ncentre) {
+    if (p->geo) return box_members(p, c, sorted_idx, ncentre);
     long long cx = c % p->ncx, cy = c / p->ncx;
     int ov = p->overlap, k = 0;
     for (long long dy = -ov; dy <= ov; ++dy) {
@@ -346,10 +445,13 @@ static int cholesky_lower(double* a, int n) {
     return 0;
 }
 
+/* number of subdomains: boxes once a geometry is set, else cells */
+static long long n_subdomains(const orc_problem* p) { return p->geo ? p->nbx * p->nby : p->ncells; }
+
 int orc_rasm_setup(orc_problem* p) {
     if (!p) return ORC_EINVAL;
     if (p->rasm_ready) return ORC_OK;
-    long long nc = p->ncells;
+    long long nc = n_subdomains(p);
     p->blk_off = (long long*)malloc(sizeof(long long) * nc);
     p->blk_n = (int*)malloc(sizeof(int) * nc);
     p->blk_nc = (int*)malloc(sizeof(int) * nc);
@@ -397,7 +499,7 @@ int orc_rasm_apply(const orc_problem* p, const double* v, double* z) {
     if (!p->rasm_ready) return ORC_ESTATE;
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
-    for (long long c = 0; c < p->ncells; ++c) {
+    for (long long c = 0; c < n_subdomains(p); ++c) {
         int k = p->blk_n[c], kc = p->blk_nc[c];
         if (kc == 0) continue;
         long long* mem = (long long*)malloc(sizeof(long long) * k);
@@ -433,7 +535,7 @@ int orc_rasm_apply(const orc_problem* p, const double* v, double* z) {
 }
 
 int orc_rasm_block_size(const orc_problem* p, long long c, int* nomega, int* ncentre) {
-    if (!p || c < 0 || c >= p->ncells) return ORC_EINVAL;
+    if (!p || c < 0 || c >= n_subdomains(p)) return ORC_EINVAL;
     int kc;
     int k = block_members(p, c, NULL, &kc);
     if (nomega) *nomega = k;
@@ -443,7 +545,7 @@ int orc_rasm_block_size(const orc_problem* p, long long c, int* nomega, int* nce
 
 int orc_rasm_block(const orc_problem* p, long long c, long long* members, int* nomega,
                    int* ncentre, double* L) {
-    if (!p || c < 0 || c >= p->ncells) return ORC_EINVAL;
+    if (!p || c < 0 || c >= n_subdomains(p)) return ORC_EINVAL;
     int kc;
     int k = block_members(p, c, NULL, &kc);
     if (nomega) *nomega = k;
@@ -459,6 +561,48 @@ int orc_rasm_block(const orc_problem* p, long long c, long long* members, int* n
         if (!p->rasm_ready || kc == 0) return ORC_ESTATE;
         memcpy(L, p->lstore + p->blk_off[c], sizeof(double) * (long long)k * k);
     }
+    return ORC_OK;
+}
+
+static void drop_factors(orc_problem* p) {
+    free(p->blk_off);
+    free(p->blk_n);
+    free(p->blk_nc);
+    free(p->lstore);
+    p->blk_off = NULL;
+    p->blk_n = NULL;
+    p->blk_nc = NULL;
+    p->lstore = NULL;
+    p->rasm_ready = 0;
+}
+
+int orc_set_geometry(orc_problem* p, double B, double D, double T) {
+    if (!p || !(B > 0.0) || !isfinite(B) || !(D >= B) || !isfinite(D) || !(T >= 0.0) ||
+        !isfinite(T) || (T > 0.0 && T < B))
+        return ORC_EINVAL;
+    double xmax = p->xs[0], ymax = p->ys[0];
+    for (long long i = 1; i < p->n; ++i) {
+        if (p->xs[i] > xmax) xmax = p->xs[i];
+        if (p->ys[i] > ymax) ymax = p->ys[i];
+    }
+    const double invB = 1.0 / B;
+    const double fx = floor((xmax - p->x0) * invB), fy = floor((ymax - p->y0) * invB);
+    if (!(fx < 1e9) || !(fy < 1e9) || (fx + 1.0) * (fy + 1.0) > 1e9) return ORC_EINVAL;
+    drop_factors(p);
+    p->geo = 1;
+    p->B = B;
+    p->D = D;
+    p->T = T;
+    p->invB = invB;
+    p->nbx = (long long)fx + 1;
+    p->nby = (long long)fy + 1;
+    return ORC_OK;
+}
+
+int orc_subdomains(const orc_problem* p, long long* nxy) {
+    if (!p || !nxy) return ORC_EINVAL;
+    nxy[0] = p->geo ? p->nbx : p->ncx;
+    nxy[1] = p->geo ? p->nby : p->ncy;
     return ORC_OK;
 }
 

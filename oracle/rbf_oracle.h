@@ -72,6 +72,18 @@ int orc_rasm_block(const orc_problem* p, long long c, long long* members,
 /* Member count of cell c's local block (to size the buffers above). */
 int orc_rasm_block_size(const orc_problem* p, long long c, int* nomega, int* ncentre);
 
+/* Subdomain geometry in lengths (Section 3.1, Fig. 3): the non-overlapping
+ * subdomains become boxes of side B on a grid anchored at the minimum point
+ * coordinates (box index by the cell rule with side B), the overlapping
+ * subdomain of a box its own points and every point of the square of side
+ * D >= B centred on it, and T > 0 (T >= B) replaces the radial cutoff of the
+ * matvec by the square of side T centred on the target's box (T = 0 keeps the
+ * radial cutoff).  Drops any RASM factors; the subdomain functions then index
+ * boxes. */
+int orc_set_geometry(orc_problem* p, double B, double D, double T);
+/* Subdomains along x and y: boxes with a geometry set, else cells. */
+int orc_subdomains(const orc_problem* p, long long* nxy);
+
 /* Right-preconditioned restarted GMRES(m) on A x = f.  x0 may be NULL (zero).
  * history (may be NULL, capacity history_cap): true relative residual at the
  * start of every cycle and at the end. */

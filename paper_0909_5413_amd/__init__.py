@@ -30,7 +30,7 @@ EXPORTED = [
     "rbf_evaluate_device", "rbf_destroy", "rbf_block_cache", "rbf_grid", "rbf_binning",
     "rbf_neighbor_counts", "rbf_matvec_device", "rbf_matvec_device_noalloc",
     "rbf_precond_apply_device",
-    "rbf_precond_block", "rbf_set_profiling", "rbf_set_graphs", "rbf_setup_kernel_times",
+    "rbf_precond_block", "rbf_set_geometry", "rbf_set_profiling", "rbf_set_graphs", "rbf_setup_kernel_times",
     "rbf_server_default_opts", "rbf_server_create", "rbf_server_submit", "rbf_server_wait",
     "rbf_server_stats", "rbf_server_destroy", "rbf_status_string", "rbf_last_error",
 ]
@@ -75,6 +75,10 @@ class SolveInfo(C.Structure):
 _lib = None
 
 
+class Geometry(C.Structure):
+    _fields_ = [("box", C.c_double), ("overlap", C.c_double)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("max_active", C.c_int), ("max_device_bytes", C.c_size_t)]
 
@@ -117,6 +121,7 @@ def lib():
         "rbf_matvec_device_noalloc": (C.c_int, [vp, vp, vp, C.c_int, vp]),
         "rbf_precond_apply_device": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
         "rbf_precond_block": (C.c_int, [vp, C.c_longlong, C.c_int, vp, vp, ip, ip]),
+        "rbf_set_geometry": (C.c_int, [vp, C.POINTER(Geometry), vp]),
         "rbf_set_profiling": (C.c_int, [vp, C.c_int]),
         "rbf_set_graphs": (C.c_int, [vp, C.c_int]),
         "rbf_server_default_opts": (None, [C.POINTER(ServerOpts)]),
@@ -297,6 +302,12 @@ def rbf_precond_apply_device(h: int, d_v, d_z, precision: int = RBF_FP64,
                              order: int = RBF_ORDER_ORIGINAL, stream=None):
     _check(lib().rbf_precond_apply_device(h, _ptr(d_v), _ptr(d_z), precision, order,
                                           _stream(stream)), "rbf_precond_apply_device")
+
+
+def rbf_set_geometry(h: int, box: float, overlap: float, stream=None):
+    """Subdomain boxes of side `box` with overlapping squares of side `overlap`."""
+    g = Geometry(float(box), float(overlap))
+    _check(lib().rbf_set_geometry(h, C.byref(g), _stream(stream)), "rbf_set_geometry")
 
 
 def rbf_set_profiling(h: int, enable: bool = True):

@@ -247,9 +247,17 @@ struct rbf_problem {
     int ntab = 0;
     float* w32 = nullptr;              // FP32 weights workspace of the FP32 matvec
 
-    // preconditioner
+    // preconditioner: its subdomains are the cells (with `overlap` layers), or
+    // after rbf_set_geometry boxes of side B with overlapping squares of side D
     std::vector<int> cs_host;          // cell_start on host
-    std::vector<int> n_omega, n_c;     // per cell
+    long long nsub = 0;                // subdomains
+    std::vector<int> n_omega, n_c;     // per subdomain
+    double xmax = 0, ymax = 0;         // largest coordinates (the box grid's extent)
+    bool geo = false;
+    rbf::BoxGeometry bg{};
+    int* mem = nullptr;                // box members (sorted-order indices), own last
+    long long* moff = nullptr;         // per box, offset into mem (nsub + 1)
+    int* nown = nullptr;               // per box, own points
     std::vector<long long> zoff_host;
     long long* zoff = nullptr;
     int np_max = 0, nc_max = 0;
@@ -388,8 +396,11 @@ struct rbf_problem {
         a.zoff = zoff;
         a.np_max = np_max;
         a.nc_max = nc_max;
-        a.ncells = ncells;
+        a.ncells = nsub;
         a.xy = nullptr;
+        a.mem = geo ? mem : nullptr;
+        a.moff = geo ? moff : nullptr;
+        a.nown = geo ? nown : nullptr;
         return a;
     }
 };
@@ -545,6 +556,8 @@ rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals,
     Grid& g = p->g;
     g.x0 = h_mm[0];
     g.y0 = h_mm[1];
+    p->xmax = h_mm[2];
+    p->ymax = h_mm[3];
     g.L = p->cutoff;
     g.invL = 1.0 / p->cutoff;
     double fx = std::floor((h_mm[2] - h_mm[0]) * g.invL);
@@ -602,6 +615,7 @@ rbf_status setup_impl(rbf_problem* p, const double* d_pts, const double* d_vals,
 
     // per-cell block sizes (host): members of the (2*ov+1)^2 block, own points
     const int ov = p->overlap;
+    p->nsub = nc;
     p->n_omega.assign(nc, 0);
     p->n_c.assign(nc, 0);
     int maxo = 0;
@@ -692,7 +706,7 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     const bool is64 = sizeof(T) == 8;
     if (is64 ? p->Z64 != nullptr : p->Z32 != nullptr) return RBF_OK;
     Timer tm;
-    const long long nc = p->ncells;
+    const long long nc = p->nsub;
     if (p->np_max > RBF_MAX_BLOCK)
         return fail(RBF_ELIMIT, "a local block has %d points, above the limit %d", p->np_max,
                     RBF_MAX_BLOCK);
@@ -1579,12 +1593,21 @@ rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d
 rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precision,
                              long long* members, double* z_rows, int* nomega, int* ncentre) {
     if (!p) return fail(RBF_EINVAL, "NULL problem");
-    if (c < 0 || c >= p->ncells) return fail(RBF_EINVAL, "cell %lld out of range", c);
+    if (c < 0 || c >= p->nsub) return fail(RBF_EINVAL, "subdomain %lld out of range", c);
     try {
         const int no = p->n_omega[c], ncn = p->n_c[c];
         if (nomega) *nomega = no;
         if (ncentre) *ncentre = ncn;
-        if (members) {
+        if (members && p->geo) {
+            std::vector<int> perm(p->n);
+            long long off = 0;
+            HIP_TRY(hipMemcpy(perm.data(), p->perm, sizeof(int) * p->n, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(&off, p->moff + c, sizeof off, hipMemcpyDeviceToHost));
+            std::vector<int> mem(no > 0 ? no : 1);
+            if (no > 0)
+                HIP_TRY(hipMemcpy(mem.data(), p->mem + off, sizeof(int) * no, hipMemcpyDeviceToHost));
+            for (int k = 0; k < no; ++k) members[k] = perm[mem[k]];
+        } else if (members) {
             std::vector<int> perm(p->n);
             HIP_TRY(hipMemcpy(perm.data(), p->perm, sizeof(int) * p->n, hipMemcpyDeviceToHost));
             const Grid& g = p->g;
@@ -1618,6 +1641,83 @@ rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precisio
         return RBF_OK;
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_precond_block");
+    }
+}
+
+rbf_status rbf_set_geometry(rbf_problem* p, const rbf_geometry* geo, void* stream) {
+    if (!p || !geo) return fail(RBF_EINVAL, "NULL argument");
+    const double B = geo->box, D = geo->overlap;
+    if (!(B > 0) || !std::isfinite(B) || !(D >= B) || !std::isfinite(D))
+        return fail(RBF_EINVAL, "need 0 < box <= overlap, both finite (got %g, %g)", B, D);
+    hipStream_t st = as_stream(stream);
+    MarkOnExit mk{p, st};
+    try {
+        const double invB = 1.0 / B;
+        const double fx = std::floor((p->xmax - p->g.x0) * invB);
+        const double fy = std::floor((p->ymax - p->g.y0) * invB);
+        if (!(fx < 1e9) || !(fy < 1e9) || (fx + 1) * (fy + 1) > 1e9)
+            return fail(RBF_EINVAL, "box grid too large: %.0f x %.0f boxes", fx + 1, fy + 1);
+        // the preconditioner of the old subdomains goes
+        if (p->Z64) p->release(p->Z64, st);
+        if (p->Z32) p->release(p->Z32, st);
+        if (p->zoff) p->release(p->zoff, st);
+        if (p->mem) p->release(p->mem, st);
+        if (p->moff) p->release(p->moff, st);
+        if (p->nown) p->release(p->nown, st);
+        p->Z64 = nullptr;
+        p->Z32 = nullptr;
+        p->zoff = nullptr;
+        p->mem = nullptr;
+        p->moff = nullptr;
+        p->nown = nullptr;
+        p->zoff_host.clear();
+        p->geo = false;
+        rbf::BoxGeometry bg;
+        bg.x0 = p->g.x0;
+        bg.y0 = p->g.y0;
+        bg.B = B;
+        bg.invB = invB;
+        bg.halfD = 0.5 * D;
+        bg.nbx = (int)fx + 1;
+        bg.nby = (int)fy + 1;
+        const long long nb = (long long)bg.nbx * bg.nby;
+        int *cnt = nullptr, *own = nullptr;
+        long long* moff = nullptr;
+        RBF_TRY(p->alloc_n(&cnt, nb));
+        RBF_TRY(p->alloc_n(&own, nb));
+        RBF_TRY(p->alloc_n(&moff, nb + 1));
+        rbf::PrecondArgs a = p->pc_args();
+        HIP_TRY(rbf::launch_box_members(a, bg, cnt, own, nullptr, nullptr, st));
+        std::vector<int> hc(nb), ho(nb);
+        HIP_TRY(hipMemcpyAsync(hc.data(), cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(ho.data(), own, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<long long> off(nb + 1, 0);
+        int maxo = 0, maxc = 0;
+        for (long long b = 0; b < nb; ++b) {
+            off[b + 1] = off[b] + hc[b];
+            if (ho[b] > 0) maxo = std::max(maxo, hc[b]);
+            maxc = std::max(maxc, ho[b]);
+        }
+        int* mem = nullptr;
+        RBF_TRY(p->alloc_n(&mem, off[nb]));
+        HIP_TRY(hipMemcpyAsync(moff, off.data(), sizeof(long long) * (nb + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(rbf::launch_box_members(a, bg, cnt, own, moff, mem, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        p->release(cnt, st);
+        p->geo = true;
+        p->bg = bg;
+        p->mem = mem;
+        p->moff = moff;
+        p->nown = own;
+        p->nsub = nb;
+        p->n_omega.assign(hc.begin(), hc.end());
+        p->n_c.assign(ho.begin(), ho.end());
+        p->np_max = (maxo + 63) / 64 * 64;
+        p->nc_max = maxc;
+        return RBF_OK;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_set_geometry");
     }
 }
 

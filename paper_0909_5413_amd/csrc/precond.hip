@@ -670,10 +670,19 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
         }
         level = lvl[slot] + 1;
     }
-    if (tid == 0)
-        block_ranges(a.cell_start, a.g, a.overlap, c, s.rb, s.re, &s.nranges, &s.n_omega, &s.n_c);
+    if (tid == 0) {
+        if (a.mem) {
+            s.n_omega = (int)(a.moff[c + 1] - a.moff[c]);
+            s.n_c = a.nown[c];
+            s.nranges = 0;
+        } else {
+            block_ranges(a.cell_start, a.g, a.overlap, c, s.rb, s.re, &s.nranges, &s.n_omega,
+                         &s.n_c);
+        }
+    }
     __syncthreads();
     const int n_omega = s.n_omega, n_c = s.n_c, nr = s.nranges;
+    const int* mlist = a.mem ? a.mem + a.moff[c] : nullptr;
     const int np = (n_omega + kFB - 1) / kFB * kFB;
     if (tid == 0) {
         meta[slot] = int4{np, n_omega, n_c, n_c > 0 ? 1 : 0};
@@ -685,7 +694,7 @@ __global__ __launch_bounds__(kT2, 2) void k_setup_assemble(PrecondArgs a, long l
     T* A = scratch + (size_t)slot * slot_elems64(a.np_max);
     double2* xy = a.xy + (size_t)slot * a.np_max;
     for (int k = tid; k < n_omega; k += kT2) {
-        const int m = member_index(s.rb, s.re, nr, k);
+        const int m = mlist ? mlist[k] : member_index(s.rb, s.re, nr, k);
         const double2 q = {a.xs[m], a.ys[m]};
         if (p + k < kFB) s.mxy[p + k] = q;
         xy[p + k] = q;
@@ -1321,27 +1330,115 @@ __global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T*
     __shared__ int nr_s, n_omega_s, n_c_s;
     const long long c = blockIdx.x;
     const int tid = threadIdx.x;
-    if (tid == 0) block_ranges(a.cell_start, a.g, a.overlap, c, rb, re, &nr_s, &n_omega_s, &n_c_s);
+    if (tid == 0) {
+        if (a.mem) {
+            n_omega_s = (int)(a.moff[c + 1] - a.moff[c]);
+            n_c_s = a.nown[c];
+            nr_s = 0;
+        } else {
+            block_ranges(a.cell_start, a.g, a.overlap, c, rb, re, &nr_s, &n_omega_s, &n_c_s);
+        }
+    }
     __syncthreads();
     const int n_omega = n_omega_s, n_c = n_c_s, nr = nr_s;
     if (n_c == 0) return;
-    for (int k = tid; k < n_omega; k += kThreads) vs[k] = (T)v[member_index(rb, re, nr, k)];
+    const int* mlist = a.mem ? a.mem + a.moff[c] : nullptr;
+    for (int k = tid; k < n_omega; k += kThreads)
+        vs[k] = (T)v[mlist ? mlist[k] : member_index(rb, re, nr, k)];
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     const int grp = lane >> 4, ph = lane & 15;
     const T* Zc = Z + a.zoff[c];
-    const int own = a.cell_start[c];
+    const int own = mlist ? 0 : a.cell_start[c];
     for (int r0 = 4 * wave; r0 < n_c; r0 += 4 * (kThreads / 64)) {
         const int r = r0 + grp;
         double sum = 0.0;
         if (r < n_c) sum = row_dot<T>(Zc + (size_t)r * n_omega, vs, n_omega, ph);
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, RBF_WAVE);
-        if (ph == 0 && r < n_c) z[own + r] = sum;
+        if (ph == 0 && r < n_c) z[mlist ? mlist[n_omega - n_c + r] : own + r] = sum;
+    }
+}
+
+// Members of box b (one wave per box): the candidate cells are those of the
+// square of side D around the box's centre, widened by one cell (rounding at
+// its edges), scanned row by row, each row's cells one contiguous sorted
+// range, so the members come out in sorted order; a first pass takes the
+// points inside the square that the box does not own, a second the box's
+// own points.  The decisions use the same arithmetic as the oracle's: box
+// index floor((x - x0) / B) clamped, centre x0 + (bx + 1/2) B, and
+// |x - centre| <= D / 2 along both axes.
+__device__ __forceinline__ int box_coord(double v, double v0, double inv, int n) {
+    double t = floor((v - v0) * inv);
+    if (!(t >= 0.0)) t = 0.0;
+    if (t > (double)(n - 1)) t = (double)(n - 1);
+    return (int)t;
+}
+
+constexpr int kBoxThreads = 256;
+
+template <bool kFill>
+__global__ __launch_bounds__(kBoxThreads) void k_box_members(PrecondArgs a, BoxGeometry bg,
+                                                            int* __restrict__ n_omega,
+                                                            int* __restrict__ n_own,
+                                                            const long long* __restrict__ moff,
+                                                            int* __restrict__ mem) {
+    const int lane = threadIdx.x & 63;
+    const long long b = (long long)blockIdx.x * (kBoxThreads / 64) + (threadIdx.x >> 6);
+    const long long nbox = (long long)bg.nbx * bg.nby;
+    if (b >= nbox) return;
+    const int bx = (int)(b % bg.nbx), by = (int)(b / bg.nbx);
+    const double cx = bg.x0 + ((double)bx + 0.5) * bg.B;
+    const double cy = bg.y0 + ((double)by + 0.5) * bg.B;
+    const double h = bg.halfD;
+    const Grid& g = a.g;
+    int xa = box_coord(cx - h, g.x0, g.invL, g.ncx) - 1, xb = box_coord(cx + h, g.x0, g.invL, g.ncx) + 1;
+    int ya = box_coord(cy - h, g.y0, g.invL, g.ncy) - 1, yb = box_coord(cy + h, g.y0, g.invL, g.ncy) + 1;
+    xa = xa < 0 ? 0 : xa;
+    ya = ya < 0 ? 0 : ya;
+    xb = xb > g.ncx - 1 ? g.ncx - 1 : xb;
+    yb = yb > g.ncy - 1 ? g.ncy - 1 : yb;
+    int* out = kFill ? mem + moff[b] : nullptr;
+    int k = 0, kc = 0;
+    for (int own = 0; own <= 1; ++own)
+        for (int ny = ya; ny <= yb; ++ny) {
+            const int j0 = a.cell_start[ny * g.ncx + xa], j1 = a.cell_start[ny * g.ncx + xb + 1];
+            for (int jb = j0; jb < j1; jb += 64) {
+                const int j = jb + lane;
+                bool take = false;
+                if (j < j1) {
+                    const double x = a.xs[j], y = a.ys[j];
+                    const bool mine = box_coord(x, bg.x0, bg.invB, bg.nbx) == bx &&
+                                      box_coord(y, bg.y0, bg.invB, bg.nby) == by;
+                    const bool inside = fabs(x - cx) <= h && fabs(y - cy) <= h;
+                    take = own ? mine : (inside && !mine);
+                }
+                const unsigned long long m = __ballot(take);
+                if (kFill && take) out[k + __popcll(m & ((1ull << lane) - 1ull))] = j;
+                const int cnt = __popcll(m);
+                k += cnt;
+                kc += own ? cnt : 0;
+            }
+        }
+    if (!kFill && lane == 0) {
+        n_omega[b] = k;
+        n_own[b] = kc;
     }
 }
 
 }  // namespace
+
+hipError_t launch_box_members(const PrecondArgs& a, const BoxGeometry& bg, int* n_omega,
+                              int* n_own, const long long* moff, int* mem, hipStream_t st) {
+    const long long nbox = (long long)bg.nbx * bg.nby;
+    const unsigned grid = (unsigned)((nbox + kBoxThreads / 64 - 1) / (kBoxThreads / 64));
+    if (nbox == 0) return hipSuccess;
+    if (mem)
+        k_box_members<true><<<grid, kBoxThreads, 0, st>>>(a, bg, n_omega, n_own, moff, mem);
+    else
+        k_box_members<false><<<grid, kBoxThreads, 0, st>>>(a, bg, n_omega, n_own, moff, mem);
+    return hipGetLastError();
+}
 
 hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const double* v, double* z,
                                hipStream_t st) {

@@ -155,7 +155,26 @@ struct PrecondArgs {
     long long ncells;
     double2* xy;            // setup only: per batch slot, np_max member coordinates
                             // (padded order; the padding rows unused)
+    // Subdomain boxes (NULL: the subdomains are the cells with `overlap`
+    // layers): members of subdomain c are mem[moff[c] .. moff[c + 1]) (sorted-
+    // order indices), the last nown[c] of them its own points.
+    const int* mem;
+    const long long* moff;
+    const int* nown;
 };
+// Subdomain boxes in lengths (Section 3.1, Fig. 3): boxes of side B on the grid
+// anchored at (x0, y0), box index by the cell rule with 1/B, the overlapping
+// subdomain of a box its own points and every point within half of D of its
+// centre along both axes.
+struct BoxGeometry {
+    double x0, y0, B, invB, halfD;
+    int nbx, nby;
+};
+// Members of every box, in sorted order with the box's own points moved last:
+// counts (n_omega[b], n_own[b]) with mem == NULL, else the indices at
+// mem[moff[b] ..].  One wave per box.
+hipError_t launch_box_members(const PrecondArgs& a, const BoxGeometry& bg, int* n_omega,
+                              int* n_own, const long long* moff, int* mem, hipStream_t st);
 // Build Z_c (centre rows of the inverse of the local matrix) for all cells, in
 // batches of nslots cells.  a.xy holds 8 * ceil(nslots / 8) * np_max entries,
 // scratch nslots * slot_elems64(np_max) elements, meta and lvl 8 * ceil(nslots / 8) entries, lt 2 * 2048 * 8 *

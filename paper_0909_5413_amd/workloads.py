@@ -86,6 +86,23 @@ def gaussian_vortex(pts: np.ndarray, r0: float = 0.2) -> np.ndarray:
     return np.exp(-r2 / (r0 * r0)) / (np.pi * r0 * r0)
 
 
+def franke(pts: np.ndarray) -> np.ndarray:
+    """Franke's test function for 2-D scattered-data fitting (the paper's test
+    data, Section 3.1), meant for points in [0, 1]^2."""
+    x, y = pts[:, 0], pts[:, 1]
+    return (0.75 * np.exp(-((9 * x - 2) ** 2 + (9 * y - 2) ** 2) / 4)
+            + 0.75 * np.exp(-((9 * x + 1) ** 2) / 49 - (9 * y + 1) / 10)
+            + 0.5 * np.exp(-((9 * x - 7) ** 2 + (9 * y - 3) ** 2) / 4)
+            - 0.2 * np.exp(-(9 * x - 4) ** 2 - (9 * y - 7) ** 2))
+
+
+def unit_square_lattice(n_side: int, h_over_sigma: float, jitter: float = 0.1, seed: int = SEED_BASE):
+    """The paper's layout (Section 3.1): a jittered n_side^2 lattice on [0, 1]^2
+    (cell-centred, spacing h = 1 / n_side), and sigma = h / (h/sigma)."""
+    pts = jittered_lattice(n_side, jitter, seed, lo=0.0, hi=1.0)
+    return pts, (1.0 / n_side) / h_over_sigma
+
+
 def random_weights(n: int, seed: int) -> np.ndarray:
     """w ~ U(-1, 1), float64, for matvec micro-benchmarks and parity tests."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n)

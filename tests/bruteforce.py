@@ -83,3 +83,71 @@ def rasm_dense(points, sigma: float, cutoff: float, overlap: int = 1):
             rows = [pos[int(g)] for g in own]
             minv[np.ix_(own, sub)] = inv[rows, :]
     return minv
+
+
+def boxes(points, B: float):
+    """Subdomain boxes of side B on the grid anchored at the minimum corner:
+    box index of every point, the box grid's size and every box's centre."""
+    x0, y0 = points[:, 0].min(), points[:, 1].min()
+    inv = 1.0 / B
+    nbx = int(np.floor((points[:, 0].max() - x0) * inv)) + 1
+    nby = int(np.floor((points[:, 1].max() - y0) * inv)) + 1
+    bx = np.clip(np.floor((points[:, 0] - x0) * inv), 0, nbx - 1).astype(np.int64)
+    by = np.clip(np.floor((points[:, 1] - y0) * inv), 0, nby - 1).astype(np.int64)
+    cx = x0 + (np.arange(nbx) + 0.5) * B
+    cy = y0 + (np.arange(nby) + 0.5) * B
+    return by * nbx + bx, nbx, nby, cx, cy
+
+
+def sorted_order(points, cutoff: float):
+    """Position of every point in the (cell, index) order of the cells of side
+    cutoff."""
+    cx, cy, ncx, _ = cells_of(points, cutoff)
+    key = (cy * ncx + cx) * points.shape[0] + np.arange(points.shape[0])
+    rank = np.empty(points.shape[0], dtype=np.int64)
+    rank[np.argsort(key)] = np.arange(points.shape[0])
+    return rank
+
+
+def box_members(points, cutoff: float, B: float, D: float, b: int):
+    """Members of box b: its own points and every point within D/2 of its centre
+    along both axes; the others first, then the own ones, each in the (cell,
+    index) order of the cells of side cutoff."""
+    box, nbx, _, cx, cy = boxes(points, B)
+    own = box == b
+    inside = ((np.abs(points[:, 0] - cx[b % nbx]) <= 0.5 * D)
+              & (np.abs(points[:, 1] - cy[b // nbx]) <= 0.5 * D))
+    rank = sorted_order(points, cutoff)
+    other = np.nonzero(inside & ~own)[0]
+    mine = np.nonzero(own)[0]
+    return np.concatenate([other[np.argsort(rank[other])], mine[np.argsort(rank[mine])]]), len(mine)
+
+
+def box_truncation_mask(points, targets, B: float, T: float):
+    """mask[t, j]: source j lies in the square of side T centred on the box of
+    target t (boxes of side B over `points`, targets clamped to the grid)."""
+    x0, y0 = points[:, 0].min(), points[:, 1].min()
+    _, nbx, nby, cx, cy = boxes(points, B)
+    inv = 1.0 / B
+    tbx = np.clip(np.floor((targets[:, 0] - x0) * inv), 0, nbx - 1).astype(np.int64)
+    tby = np.clip(np.floor((targets[:, 1] - y0) * inv), 0, nby - 1).astype(np.int64)
+    h = 0.5 * T
+    return ((np.abs(points[None, :, 0] - cx[tbx][:, None]) <= h)
+            & (np.abs(points[None, :, 1] - cy[tby][:, None]) <= h))
+
+
+def rasm_dense_boxes(points, sigma: float, cutoff: float, B: float, D: float):
+    """Explicit M^{-1} of RASM over the boxes, numpy.linalg.inv of each
+    untruncated local matrix, only the rows of the box's own points kept."""
+    n = points.shape[0]
+    box, nbx, nby, _, _ = boxes(points, B)
+    minv = np.zeros((n, n))
+    for b in range(nbx * nby):
+        mem, kc = box_members(points, cutoff, B, D, b)
+        if kc == 0:
+            continue
+        pts = points[mem]
+        d2, _, _ = pair_d2(pts[:, 0], pts[:, 1], pts[:, 0], pts[:, 1])
+        inv = np.linalg.inv(gaussian(d2, sigma))
+        minv[np.ix_(mem[len(mem) - kc:], mem)] = inv[len(mem) - kc:, :]
+    return minv

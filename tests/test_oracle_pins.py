@@ -368,3 +368,133 @@ def test_nan_residual(oracle_mod):
     P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
     _, info = P.gmres(np.full(w.n, 1e200), 30, 1e-10, raise_on_error=False)
     assert info.status == 8
+
+
+# ------------------------------------------- subdomains and truncation in lengths
+def paper_lattice(n_side, ratio, seed=5):
+    """The paper's layout (Section 3.1): [0, 1]^2, sigma = h / (h/sigma)."""
+    pts, sigma = W.unit_square_lattice(n_side, ratio, seed=seed)
+    return pts, sigma
+
+
+@pytest.mark.parametrize("Bs,Dr", [(5.0, 1.9), (3.0, 2.3), (7.0, 1.5)])
+def test_box_members_bruteforce(oracle_mod, Bs, Dr):
+    """Every box's members (Section 3.1, Fig. 3: non-overlapping boxes of side
+    B, overlapping squares of side D) against a brute-force scan; every point
+    is owned by exactly one box."""
+    pts, sigma = paper_lattice(36, 0.9)
+    cutoff = 6 * sigma
+    B, D = Bs * sigma, Dr * Bs * sigma
+    P = oracle_mod.Problem(pts, sigma, cutoff)
+    P.set_geometry(B, D)
+    nbx, nby = P.subdomains()
+    box, bnx, bny, _, _ = bf.boxes(pts, B)
+    assert (nbx, nby) == (bnx, bny)
+    owned = np.zeros(pts.shape[0], dtype=int)
+    for b in range(nbx * nby):
+        mem, kc, _ = P.rasm_block(b, with_factor=False)
+        ref, rkc = bf.box_members(pts, cutoff, B, D, b)
+        assert kc == rkc and np.array_equal(mem, ref)
+        owned[mem[len(mem) - kc:]] += 1
+    assert np.all(owned == 1)
+
+
+def test_box_rasm_matches_explicit_inverse(oracle_mod):
+    pts, sigma = paper_lattice(30, 0.9)
+    cutoff = 6 * sigma
+    B, D = 5 * sigma, 1.9 * 5 * sigma
+    P = oracle_mod.Problem(pts, sigma, cutoff)
+    P.set_geometry(B, D)
+    P.rasm_setup()
+    v = W.random_weights(pts.shape[0], 51)
+    z = P.rasm_apply(v)
+    ref = bf.rasm_dense_boxes(pts, sigma, cutoff, B, D) @ v
+    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_cells_as_boxes_reproduce_cell_subdomains(oracle_mod):
+    """B = the cell side and D = 3B give the same subdomains, in the same
+    order, as the cells with one layer of overlap (no point on a box edge)."""
+    w, pts = lattice(40, 0.8)
+    P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    Q = oracle_mod.Problem(pts, w.sigma, w.cutoff)
+    Q.set_geometry(w.cutoff, 3 * w.cutoff)
+    assert Q.subdomains() == (P.ncx, P.ncy)
+    for c in range(P.ncells):
+        m1, k1, _ = P.rasm_block(c, with_factor=False)
+        m2, k2, _ = Q.rasm_block(c, with_factor=False)
+        assert k1 == k2 and np.array_equal(m1, m2)
+
+
+@pytest.mark.parametrize("margin", [4.0, 2.0])
+def test_box_truncation_matvec_bruteforce(oracle_mod, margin):
+    """The matvec truncated to the box widened by a margin (the square of side
+    T = B + 2 margin centred on the target's box, Section 3.1) against the
+    dense matrix with that mask built by brute force; neighbour counts exact;
+    evaluation off the nodes with the same rule.  The matrix is not symmetric."""
+    pts, sigma = paper_lattice(32, 0.9)
+    B = 5 * sigma
+    T = B + 2 * margin * sigma
+    cutoff = B + margin * sigma     # cells at least as wide as a target's reach
+    P = oracle_mod.Problem(pts, sigma, cutoff)
+    P.set_geometry(B, 1.9 * B, T)
+    v = W.random_weights(pts.shape[0], 52)
+    y, nnb = P.matvec(v, with_counts=True)
+    mask = bf.box_truncation_mask(pts, pts, B, T)
+    d2, _, _ = bf.pair_d2(pts[:, 0], pts[:, 1], pts[:, 0], pts[:, 1])
+    A = np.where(mask, bf.gaussian(d2, sigma), 0.0)
+    assert not np.array_equal(A, A.T)
+    assert np.array_equal(nnb, mask.sum(axis=1))
+    assert np.all(np.abs(y - A @ v) <= 1e-14 * (np.abs(A) @ np.abs(v)))
+    tg, _ = W.evaluation_targets(pts, cutoff)
+    mt = bf.box_truncation_mask(pts, tg, B, T)
+    d2t, _, _ = bf.pair_d2(tg[:, 0], tg[:, 1], pts[:, 0], pts[:, 1])
+    K = np.where(mt, bf.gaussian(d2t, sigma), 0.0)
+    s = P.evaluate(v, tg)
+    # d^2 rounded twice here, once fused in the oracle: each term differs by
+    # up to 2 u d^2 / (2 sigma^2) relative, which matters for the targets far
+    # outside the point set (exponents near -70)
+    expo = np.where(mt, d2t / (2 * sigma * sigma), 0.0).max(axis=1)
+    bar = (1e-14 + 4 * 2.0 ** -53 * expo) * (K @ np.abs(v))
+    assert np.all(np.abs(s - K @ v) <= bar)
+
+
+def test_box_geometry_gmres_matches_dense_solve(oracle_mod):
+    """GMRES on the box-truncated (non-symmetric) system with box subdomains
+    reaches the dense LU solution of that system."""
+    pts, sigma = paper_lattice(30, 1.0)
+    B = 5 * sigma
+    T = B + 8 * sigma
+    P = oracle_mod.Problem(pts, sigma, B + 4 * sigma)
+    P.set_geometry(B, 1.9 * B, T)
+    f = W.franke(pts)
+    x, info = P.gmres(f, 30, 1e-12)
+    assert info.status == 0
+    mask = bf.box_truncation_mask(pts, pts, B, T)
+    d2, _, _ = bf.pair_d2(pts[:, 0], pts[:, 1], pts[:, 0], pts[:, 1])
+    A = np.where(mask, bf.gaussian(d2, sigma), 0.0)
+    assert np.linalg.norm(f - A @ x) / np.linalg.norm(f) <= 1.5e-12
+    xd = np.linalg.solve(A, f)
+    assert np.linalg.norm(x - xd) <= np.linalg.cond(A) * 3e-12 * np.linalg.norm(xd)
+
+
+def test_iterations_against_subdomain_sizes(oracle_mod):
+    """Section 3.2 (Figs. 4 and 6) on a 60 x 60 lattice on [0, 1]^2 with
+    Franke data, B = 5 sigma, D = 1.9 B and the matvec truncated to the box
+    widened by 4 sigma (6 sigma at h/sigma = 0.8): convergence to 1e-13 within
+    about 20 iterations at h/sigma = 1.0, more at 0.9 and markedly more at 0.8;
+    at fixed B, a wider overlap D needs fewer iterations (1.5 B -> 1.9 B);
+    larger boxes need fewer."""
+    def iters(ratio, Bs, Dr):
+        pts, sigma = paper_lattice(60, ratio)
+        m = 6.0 if ratio < 0.85 else 4.0
+        B = Bs * sigma
+        P = oracle_mod.Problem(pts, sigma, B + m * sigma)
+        P.set_geometry(B, Dr * B, B + 2 * m * sigma)
+        _, info = P.gmres(W.franke(pts), 30, 1e-13, max_iters=400)
+        assert info.status == 0
+        return info.iterations
+    i10, i09, i08 = iters(1.0, 5, 1.9), iters(0.9, 5, 1.9), iters(0.8, 5, 1.9)
+    assert i10 <= 22 and i10 < i09 < i08 and i08 >= 1.5 * i10, (i10, i09, i08)
+    assert iters(0.9, 5, 1.5) > i09
+    assert iters(0.9, 7, 1.9) < i09 < iters(0.9, 3, 1.9)
