@@ -81,14 +81,14 @@ def profiled_traffic(kernel):
     return None
 
 
-def serving_run(R, W, k, precision, max_active, max_iters):
+def serving_run(R, W, k, precision, max_active, max_iters, packed=2, n_hi=1e6):
     """The request stream of the serving configuration through rbf_server_*:
     a closed-loop run (all k requests submitted at once) measures the capacity
     in solves/s, then an open-loop run submits the same requests at Poisson
     arrival times with 0.7x that rate and records each request's latency
     (submission to completion, the server's steady clock)."""
     import numpy as np
-    reqs = W.serving_requests(k)
+    reqs = W.serving_requests(k, n_hi=n_hi)
     data = []
     for w in reqs:
         p = w.points()
@@ -100,7 +100,7 @@ def serving_run(R, W, k, precision, max_active, max_iters):
                                                   max_iters=max_iters))
 
     everything = tuple(range(11))
-    srv = R.rbf_server_create(max_active=max_active)
+    srv = R.rbf_server_create(max_active=max_active, packed=packed)
     try:
         t0 = time.perf_counter()
         ids = [submit(srv, w, p, f) for w, p, f in data]
@@ -111,7 +111,7 @@ def serving_run(R, W, k, precision, max_active, max_iters):
     cap = k / makespan
     rate = 0.7 * cap
     arrivals = np.cumsum(np.random.default_rng(W.SEED_BASE * 1000 + 999).exponential(1.0 / rate, k))
-    srv = R.rbf_server_create(max_active=max_active)
+    srv = R.rbf_server_create(max_active=max_active, packed=packed)
     try:
         t0 = time.perf_counter()
         ids = []
@@ -126,9 +126,13 @@ def serving_run(R, W, k, precision, max_active, max_iters):
         R.rbf_server_destroy(srv)
     lat = np.array([r.latency for _, r, _ in opened])
     status = [st for _, _, st in opened]
+    conv = np.array([r.latency for _, r, st in opened if st == R.RBF_OK])
     return {
         "requests": k, "precision": "fp64" if precision == R.RBF_FP64 else "mixed",
-        "max_active": max_active, "max_iters": max_iters,
+        "mode": f"{packed} packed engines" if packed else "one stream per request",
+        "max_active": max_active, "max_iters": max_iters, "n_hi": n_hi,
+        "converged_latency_p50_s": float(np.percentile(conv, 50)) if conv.size else None,
+        "converged_latency_p99_s": float(np.percentile(conv, 99)) if conv.size else None,
         "capacity_solves_per_s": cap, "offered_rate_per_s": rate,
         "completed_solves_per_s": k / span,
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
@@ -165,6 +169,40 @@ def event_median(torch, stream, fn, warmup, reps):
         b.record(stream)
     ev[-1][1].synchronize()
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def eval_run(R, torch, w, d_pts, d_f, d_lam, stream, opts):
+    """rbf_evaluate_device at two target sets of about N points each, after an
+    FP64 solve: its median time over 20 event-timed calls after 3, the
+    in-cutoff interactions it sums (rbf_target_counts_device) and their rate
+    against R64."""
+    import numpy as np
+    from paper_0909_5413_amd import workloads as W
+    lo = d_pts.min(dim=0).values.cpu().numpy()
+    hi = d_pts.max(dim=0).values.cpu().numpy()
+    sets = {"staggered_lattice": W.staggered_lattice(w.n_side),
+            "uniform": np.random.default_rng(W.SEED_BASE + 21).uniform(lo, hi, (w.n, 2))}
+    out = {}
+    h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+    try:
+        R.rbf_precond_setup(h, R.RBF_FP64, stream)
+        R.rbf_solve_device(h, d_lam, opts)
+        for name, tg in sets.items():
+            d_t = torch.tensor(tg, device=d_pts.device)
+            m = tg.shape[0]
+            d_s = torch.empty(m, device=d_pts.device, dtype=torch.float64)
+            d_c = torch.empty(m, device=d_pts.device, dtype=torch.int32)
+            R.rbf_target_counts_device(h, d_t, m, d_c, stream)
+            inter = int(d_c.to(torch.int64).sum().item())
+            ms = event_median(torch, stream, lambda: R.rbf_evaluate_device(h, d_t, m, d_s, stream),
+                              3, 20)
+            rate = inter / (ms * 1e-3)
+            out[name] = {"targets": m, "ms": ms, "evaluations_per_s": m / (ms * 1e-3),
+                         "interactions": inter, "interactions_per_s": rate,
+                         "frac_r64": rate * OPS_PER_INTERACTION / VALU_OPS_PER_S}
+    finally:
+        R.rbf_destroy(h)
+    return out
 
 
 def geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, B, D, precision, reps=3):
@@ -263,12 +301,19 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-geometry", action="store_true")
+    ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--sweep-geometry", action="store_true",
                     help="also time B in {3..7} sigma x D/B in {1.5..2.3} (Figs. 6 and 7)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving stream to run (the configuration's 512)")
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-max-iters", type=int, default=300)
+    ap.add_argument("--serve-engines", type=int, default=2,
+                    help="packed engines of the server (0: one stream per request)")
+    ap.add_argument("--serve-n-hi", type=float, default=1e6,
+                    help="largest request size of the stream (the configuration's 1e6)")
+    ap.add_argument("--serve-compare", type=str, default="",
+                    help="comma-separated further engine counts to serve the stream with")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -458,6 +503,14 @@ def main():
                  "evaluate_ms": t_ev, "evaluations_per_s": tg.shape[0] / (t_ev * 1e-3)}
         log("mixed", mixed)
 
+    # ---- evaluation of the interpolant at separate targets (eq. rbf1; the
+    # remeshing use): the staggered lattice between the nodes and seeded
+    # uniform points over the nodes' box, in-cutoff interactions per second
+    evaluation = None
+    if not args.no_eval:
+        evaluation = eval_run(R, torch, w, d_pts, d_f, d_lam, stream, opts)
+        log("evaluation", evaluation)
+
     # ---- the paper's subdomain geometry: boxes of side B, overlapping squares of
     # side D (its measured optimum B = 5 sigma, D = 1.9 B) against the 3x3 cells
     geometry = None
@@ -474,8 +527,14 @@ def main():
         for tag, prec in (("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED)):
             log("serving", tag, args.serve_requests, "requests")
             serving[tag] = serving_run(R, W, args.serve_requests, prec, args.serve_active,
-                                       args.serve_max_iters)
+                                       args.serve_max_iters, packed=args.serve_engines,
+                                       n_hi=args.serve_n_hi)
             log("serving", tag, serving[tag])
+            for e in (int(v) for v in args.serve_compare.split(",") if v.strip()):
+                serving[f"{tag}_engines{e}"] = serving_run(R, W, args.serve_requests, prec,
+                                                           args.serve_active, args.serve_max_iters,
+                                                           packed=e, n_hi=args.serve_n_hi)
+                log("serving", tag, e, "engines", serving[f"{tag}_engines{e}"])
 
     cpu = None
     if not args.no_cpu:
@@ -502,6 +561,7 @@ def main():
         "p99_latency_s": serving["fp64"]["latency_p99_s"] if serving else None,
         "serving": serving,
         "geometry": geometry,
+        "evaluation": evaluation,
         "roofline": roofline,
         "kernels": kernels,
         "setup_kernels_ms": {k: {"ms": v[0], "launches": v[1]} for k, v in setup_k.items()},

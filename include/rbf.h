@@ -166,6 +166,14 @@ rbf_status rbf_evaluate(const rbf_problem* p, const double* targets, long long m
 rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, long long m,
                                double* d_out, void* stream);
 
+/* The number of sources the interpolant sums at each of m targets (device
+ * arrays: targets m x 2, counts m ints, original target order): the in-cutoff
+ * neighbours of eq. rbf1's truncated sum, found as rbf_evaluate_device finds
+ * them (target cells clamped to the grid).  Needs no solve.  Errors:
+ * RBF_EINVAL (NULL, m < 0, NaN or Inf in the targets). */
+rbf_status rbf_target_counts_device(const rbf_problem* p, const double* d_targets, long long m,
+                                    int* d_counts, void* stream);
+
 /* Release everything the handle owns (NULL is ignored).  Waits for the work
  * that the handle's calls enqueued and no other work, through an event
  * recorded on the stream of the handle's last call, which must therefore
@@ -278,17 +286,38 @@ rbf_status rbf_setup_kernel_times(const rbf_problem* p, rbf_precision precision,
 /* Requests are admitted in arrival order whenever fewer than max_active are
  * on the device and their predicted device footprint fits what the budget has
  * left (a request larger than the whole budget is admitted alone); each
- * admitted request runs setup, preconditioner and solve on its own HIP stream
+ * admitted request runs its setup and preconditioner on its own HIP stream
  * from a worker thread, so requests that arrive while others run join as
- * slots and memory free up and their kernels overlap on the device.  A
- * request's launches are those of a lone rbf_solve_device call: its weights do
- * not depend on the mix. */
+ * slots and memory free up and their kernels overlap on the device.  Its solve
+ * then joins a packed engine at the next step boundary (packed > 0, up to
+ * pack_max_points points): an engine thread advances every solve it holds by
+ * one GMRES step per engine step, each kernel of the step (the RASM applies, the matvecs, the
+ * Gram-Schmidt passes) launched once for all requests over a (request, unit)
+ * job table, the step captured as a HIP graph per set of requests; with
+ * packed = 0 each request solves alone on its worker's stream.  Either way a
+ * request's arithmetic is that of a lone rbf_solve_device call, with the same
+ * per-request reductions: its weights do not depend on the mix. */
 typedef struct rbf_server rbf_server;   /* opaque; created by rbf_server_create */
 
 typedef struct {
     int max_active;            /* requests on the device at once, 1..64 (default 8) */
     size_t max_device_bytes;   /* admission budget; 0 = 90% of the device memory free
                                   at creation */
+    int packed;                /* engines, 0..8 (default 2): each engine advances the
+                                  solves it holds together, each engine step one
+                                  Arnoldi step (or cycle end) of every one of them,
+                                  every kernel of the step launched once for all;
+                                  new solves go to the engine holding the fewest, so
+                                  one engine's host work overlaps the others' steps;
+                                  0: each request solves alone on its worker's stream */
+    int graphs;                /* packed: capture a step's launches once per set of
+                                  active requests as a HIP graph and replay it
+                                  (default 1) */
+    long long pack_max_points; /* packed: requests with more points solve alone on
+                                  their worker's stream (their kernels fill the
+                                  device by themselves, and in lockstep they would
+                                  hold the small ones back); 0 = no limit
+                                  (default 65536) */
 } rbf_server_opts;
 
 typedef struct {

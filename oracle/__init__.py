@@ -58,6 +58,7 @@ def lib():
         L.orc_binning.argtypes = [vp, ip, ip, lp]
         L.orc_matvec.argtypes = [vp, dp, dp, ip]
         L.orc_evaluate.argtypes = [vp, dp, dp, C.c_longlong, dp]
+        L.orc_evaluate_counts.argtypes = [vp, dp, dp, C.c_longlong, dp, ip]
         L.orc_rasm_setup.argtypes = [vp]
         L.orc_rasm_apply.argtypes = [vp, dp, dp]
         L.orc_rasm_block.argtypes = [vp, C.c_longlong, lp, ip, ip, dp]
@@ -163,14 +164,15 @@ class Problem:
             raise OracleError(rc, "orc_matvec")
         return (y, nnb) if with_counts else y
 
-    def evaluate(self, lam, targets):
+    def evaluate(self, lam, targets, with_counts: bool = False):
         lam = np.ascontiguousarray(lam, dtype=np.float64)
         t = np.ascontiguousarray(targets, dtype=np.float64).reshape(-1, 2)
         out = np.empty(t.shape[0])
-        rc = lib().orc_evaluate(self._h, _dp(lam), _dp(t), t.shape[0], _dp(out))
+        nnb = np.empty(t.shape[0], dtype=np.int32) if with_counts else None
+        rc = lib().orc_evaluate_counts(self._h, _dp(lam), _dp(t), t.shape[0], _dp(out), _ip(nnb))
         if rc:
             raise OracleError(rc, "orc_evaluate")
-        return out
+        return (out, nnb) if with_counts else out
 
     def rasm_setup(self):
         rc = lib().orc_rasm_setup(self._h)

@@ -348,6 +348,11 @@ int orc_matvec(const orc_problem* p, const double* w, double* y, int* nnb) {
 
 int orc_evaluate(const orc_problem* p, const double* lambda, const double* targets,
                  long long m, double* out) {
+    return orc_evaluate_counts(p, lambda, targets, m, out, NULL);
+}
+
+int orc_evaluate_counts(const orc_problem* p, const double* lambda, const double* targets,
+                        long long m, double* out, int* nnb) {
     if (!p || !lambda || (m > 0 && (!targets || !out)) || m < 0) return ORC_EINVAL;
     for (long long t = 0; t < 2 * m; ++t)
         if (!isfinite(targets[t])) return ORC_EINVAL;
@@ -360,7 +365,9 @@ int orc_evaluate(const orc_problem* p, const double* lambda, const double* targe
         long long cx, cy;
         double x = targets[2 * t], y = targets[2 * t + 1];
         cell_index(p, x, y, &cx, &cy);
-        out[t] = cell_sum(p, x, y, cx, cy, ws, NULL);
+        int cnt;
+        out[t] = cell_sum(p, x, y, cx, cy, ws, &cnt);
+        if (nnb) nnb[t] = cnt;
     }
     free(ws);
     return ORC_OK;

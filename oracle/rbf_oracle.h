@@ -59,6 +59,10 @@ int orc_matvec(const orc_problem* p, const double* w, double* y, int* nnb);
 /* out[t] = sum_j lambda_j phi(|target_t - x_j|) over sources within the cutoff. */
 int orc_evaluate(const orc_problem* p, const double* lambda, const double* targets,
                  long long m, double* out);
+/* As orc_evaluate, and nnb[t] (may be NULL) = the number of sources summed for
+ * target t (the target's in-cutoff neighbours). */
+int orc_evaluate_counts(const orc_problem* p, const double* lambda, const double* targets,
+                        long long m, double* out, int* nnb);
 
 /* RASM: factor every local block (dense Cholesky), then z = M^{-1} v. */
 int orc_rasm_setup(orc_problem* p);

@@ -27,7 +27,7 @@ RBF_NOALLOC_MAX_POINTS = 4194304
 EXPORTED = [
     "rbf_default_opts", "rbf_setup", "rbf_setup_device", "rbf_set_values",
     "rbf_precond_setup", "rbf_solve", "rbf_solve_device", "rbf_evaluate",
-    "rbf_evaluate_device", "rbf_destroy", "rbf_block_cache", "rbf_grid", "rbf_binning",
+    "rbf_evaluate_device", "rbf_target_counts_device", "rbf_destroy", "rbf_block_cache", "rbf_grid", "rbf_binning",
     "rbf_neighbor_counts", "rbf_matvec_device", "rbf_matvec_device_noalloc",
     "rbf_precond_apply_device",
     "rbf_precond_block", "rbf_set_geometry", "rbf_set_profiling", "rbf_set_graphs", "rbf_setup_kernel_times",
@@ -80,7 +80,8 @@ class Geometry(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("max_active", C.c_int), ("max_device_bytes", C.c_size_t)]
+    _fields_ = [("max_active", C.c_int), ("max_device_bytes", C.c_size_t), ("packed", C.c_int),
+                ("graphs", C.c_int), ("pack_max_points", C.c_longlong)]
 
 
 class RequestResult(C.Structure):
@@ -112,6 +113,7 @@ def lib():
         "rbf_solve_device": (C.c_int, [vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveInfo)]),
         "rbf_evaluate": (C.c_int, [vp, vp, C.c_longlong, vp]),
         "rbf_evaluate_device": (C.c_int, [vp, vp, C.c_longlong, vp, vp]),
+        "rbf_target_counts_device": (C.c_int, [vp, vp, C.c_longlong, vp, vp]),
         "rbf_destroy": (None, [vp]),
         "rbf_block_cache": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
         "rbf_grid": (C.c_int, [vp, dp, lp]),
@@ -251,6 +253,11 @@ def rbf_evaluate_device(h: int, d_targets, m: int, d_out, stream=None):
            "rbf_evaluate_device")
 
 
+def rbf_target_counts_device(h: int, d_targets, m: int, d_counts, stream=None):
+    _check(lib().rbf_target_counts_device(h, _ptr(d_targets), m, _ptr(d_counts), _stream(stream)),
+           "rbf_target_counts_device")
+
+
 def rbf_destroy(h: int):
     if h:
         lib().rbf_destroy(h)
@@ -326,11 +333,17 @@ def rbf_setup_kernel_times(h: int, precision: int = RBF_FP64) -> dict:
     return {SETUP_KERNELS[k]: (ms[k], n[k]) for k in range(RBF_K_SETUP_KINDS)}
 
 
-def rbf_server_create(max_active: int = 8, max_device_bytes: int = 0) -> int:
+def rbf_server_create(max_active: int = 8, max_device_bytes: int = 0, packed: int = 2,
+                      graphs: bool = True, pack_max_points: int = 65536) -> int:
+    """packed: number of packed engines (0: one stream per request); requests
+    above pack_max_points points (0: no limit) solve alone."""
     o = ServerOpts()
     lib().rbf_server_default_opts(C.byref(o))
     o.max_active = max_active
     o.max_device_bytes = max_device_bytes
+    o.packed = int(packed)
+    o.graphs = 1 if graphs else 0
+    o.pack_max_points = int(pack_max_points)
     h = C.c_void_p()
     _check(lib().rbf_server_create(C.byref(o), C.byref(h)), "rbf_server_create")
     return h.value

@@ -293,6 +293,7 @@ struct rbf_problem {
     double kms[2][RBF_K_SETUP_KINDS] = {};
     int kcount[2][RBF_K_SETUP_KINDS] = {};
     std::vector<double> history;
+    rbf_solve_info last_info{};        // of the last solve the packed engine ran
 
     rbf_status alloc(void** out, size_t bytes_) {
         const size_t want = BlockCache::round(bytes_);
@@ -1275,9 +1276,10 @@ rbf_status count_interactions(rbf_problem* p, int* d_nnb_sorted, hipStream_t st)
 }
 
 rbf_status evaluate_impl(const rbf_problem* cp, const double* d_t, long long m, double* d_out,
-                         hipStream_t st) {
+                         hipStream_t st, int* d_counts = nullptr) {
     rbf_problem* p = const_cast<rbf_problem*>(cp);
-    if (!p->solved || !p->lam) return fail(RBF_ESTATE, "evaluate needs a successful solve first");
+    if (!d_counts && (!p->solved || !p->lam))
+        return fail(RBF_ESTATE, "evaluate needs a successful solve first");
     if (m == 0) return RBF_OK;
     if (m < 0 || !d_t || !d_out) return fail(RBF_EINVAL, "bad targets");
     const long long nc = p->ncells;
@@ -1310,8 +1312,17 @@ rbf_status evaluate_impl(const rbf_problem* cp, const double* d_t, long long m, 
     a.tx = tx;
     a.ty = ty;
     a.tcell = tcs;
-    HIP_TRY(rbf::launch_matvec64(a, p->lam, yo, nullptr, st));
-    HIP_TRY(rbf::launch_unpermute(yo, tperm, m, d_out, st));
+    if (d_counts) {   // the targets' in-cutoff counts: the product of the data f
+        int* cnt_sorted;
+        RBF_TRY(p->alloc_n(&cnt_sorted, m));
+        HIP_TRY(rbf::launch_matvec64(a, p->fs, yo, cnt_sorted, st));
+        HIP_TRY(rbf::launch_unpermute_int(cnt_sorted, tperm, m, d_counts, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        p->release(cnt_sorted, st);
+    } else {
+        HIP_TRY(rbf::launch_matvec64(a, p->lam, yo, nullptr, st));
+        HIP_TRY(rbf::launch_unpermute(yo, tperm, m, d_out, st));
+    }
     int hflag = 0;
     HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1324,6 +1335,613 @@ rbf_status evaluate_impl(const rbf_problem* cp, const double* d_t, long long m, 
 }
 
 }  // namespace
+
+// ---- the packed solve engine -------------------------------------------------
+// Advances the GMRES(m) solves of several prepared problems together: one
+// engine step runs, for every active problem, one Arnoldi step, or the start
+// (x = 0, ||f||) or the end of a cycle with its true residual, and every
+// kernel of the step is launched once for all problems through device job
+// tables.  Each problem runs exactly the operations of solve_impl, in the same
+// order and with the same per-problem block decompositions, so its weights are
+// bit-identical to a lone solve; the host keeps each problem's Givens
+// recurrence.  A step is a fixed sequence of phases and every problem holds one
+// job slot per phase (marked idle when its state needs no work there), so the
+// step's launches depend only on the set of active problems: with graphs on,
+// they are captured once per set as a HIP graph whose first node copies the
+// step's job tables from pinned host memory, and replayed every step.
+namespace rbf {
+
+namespace {
+
+enum : int {   // vector phases of a step, in launch order
+    kVPrep = 0,    // x = 0 | V_0 = r / ||r|| | w = V y
+    kVUpd,         // x += z
+    kVSub,         // r = f - w
+    kVAxpy1,       // w -= V h1
+    kVAxpy2,       // w -= V h2
+    kVScale,       // V_{j+1} = w / ||w||
+    kVPhases
+};
+
+struct EngResult {   // per problem, written by the step's reductions
+    double h1[64], h2[64], n2;
+};
+
+struct EngProb {
+    rbf_problem* p = nullptr;
+    rbf_solve_opts o{};
+    double* lam_out = nullptr;
+    void* tag = nullptr;
+    bool mixed = false;
+    int m = 30;
+    enum St { kInit, kResid, kArnoldi, kUpdate } st = kInit;
+    bool start_cycle = false;
+    int j = 0, k = 0;
+    std::vector<double> H, cs, sn, gv, yv;
+    double bnorm = 0, rel = 0, tol_abs = 0, est = 0;
+    int iters = 0, cycles = 0, outer = 0, mv64 = 0, mv32 = 0, pc = 0;
+    bool breakdown = false;
+    int slot = -1;   // its result slot, kept while it is active
+    // block counts of its jobs
+    int nb_vec = 0, nb_dot = 0, ngroups = 0, nsub = 0;
+};
+
+}  // namespace
+
+class Engine {
+public:
+    hipStream_t st = nullptr;
+    int cap = 0;
+    bool use_graphs = false;
+    std::vector<EngProb> act;         // active problems, in join order
+    std::vector<EngProb> joining;     // added since the last step
+    // tables: pinned host staging and its device copy, laid out for the current set
+    char* h_tab = nullptr;
+    char* d_tab = nullptr;
+    size_t tab_bytes = 0, tab_cap = 0;
+    EngResult* d_res = nullptr;       // cap results, one slot per active problem
+    EngResult* h_res = nullptr;       // pinned
+    std::vector<int> free_slots;
+    double* d_coef = nullptr;         // cap x 64 update coefficients (inside the tables)
+    struct Layout {
+        size_t vec[kVPhases], bvec[kVPhases], dot[3], bdot[3], bred[3], mv, bmv, rasm, brasm, coef;
+        int nvec[kVPhases], ndot[3], nred[3], nmv, nrasm, mv_threads;
+    } L{};
+    bool layout_valid = false;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev_done = nullptr;
+
+    ~Engine() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (ev_done) (void)hipEventDestroy(ev_done);
+        if (h_tab) (void)hipHostFree(h_tab);
+        if (d_tab) (void)hipFree(d_tab);
+        if (d_res) (void)hipFree(d_res);
+        if (h_res) (void)hipHostFree(h_res);
+    }
+
+    template <typename J>
+    J* host(size_t off) { return reinterpret_cast<J*>(h_tab + off); }
+    template <typename J>
+    J* dev(size_t off) { return reinterpret_cast<J*>(d_tab + off); }
+
+    // offsets of every table for the active set, and their block offsets
+    hipError_t plan() {
+        const int na = (int)act.size();
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 255) / 256 * 256;
+            return o;
+        };
+        for (int v = 0; v < kVPhases; ++v) {
+            L.vec[v] = take(sizeof(VecJob) * na);
+            L.bvec[v] = take(sizeof(int) * (na + 1));
+        }
+        for (int d = 0; d < 3; ++d) {
+            L.dot[d] = take(sizeof(DotJob) * na);
+            L.bdot[d] = take(sizeof(int) * (na + 1));
+            L.bred[d] = take(sizeof(int) * (na + 1));
+        }
+        L.mv = take(sizeof(MatvecJob) * na);
+        L.bmv = take(sizeof(int) * (na + 1));
+        L.rasm = take(sizeof(RasmJob) * na);
+        L.brasm = take(sizeof(int) * (na + 1));
+        L.coef = take(sizeof(double) * 64 * na);
+        tab_bytes = off;
+        if (tab_bytes > tab_cap) {
+            if (h_tab) (void)hipHostFree(h_tab);
+            if (d_tab) (void)hipFree(d_tab);
+            h_tab = nullptr;
+            d_tab = nullptr;
+            tab_cap = 0;
+            hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h_tab), tab_bytes);
+            if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_tab), tab_bytes);
+            if (e != hipSuccess) return e;
+            tab_cap = tab_bytes;
+        }
+        // block offsets: fixed per problem, whatever its state
+        auto offsets = [&](size_t o, auto count) {
+            int* b = host<int>(o);
+            b[0] = 0;
+            for (int q = 0; q < na; ++q) b[q + 1] = b[q] + count(act[q]);
+            return b[na];
+        };
+        for (int v = 0; v < kVPhases; ++v) L.nvec[v] = offsets(L.bvec[v], [](const EngProb& q) { return q.nb_vec; });
+        for (int d = 0; d < 3; ++d) {
+            L.ndot[d] = offsets(L.bdot[d], [](const EngProb& q) { return q.nb_dot; });
+            L.nred[d] = offsets(L.bred[d], [](const EngProb& q) { return q.m + 1; });
+        }
+        L.nmv = offsets(L.bmv, [](const EngProb& q) { return q.ngroups; });
+        L.nrasm = offsets(L.brasm, [](const EngProb& q) { return q.nsub; });
+        L.mv_threads = 64;
+        for (const EngProb& q : act) L.mv_threads = std::max(L.mv_threads, 64 * q.p->nl.gunits);
+        d_coef = dev<double>(L.coef);
+        layout_valid = true;
+        return hipSuccess;
+    }
+
+    // the launches of one step, on stream s (captured or not)
+    hipError_t enqueue(hipStream_t s) {
+        const int na = (int)act.size();
+        hipError_t e = hipMemcpyAsync(d_tab, h_tab, tab_bytes, hipMemcpyHostToDevice, s);
+        auto vec = [&](int v) {
+            if (e == hipSuccess)
+                e = launch_vec_packed(dev<VecJob>(L.vec[v]), dev<int>(L.bvec[v]), na, L.nvec[v], s);
+        };
+        auto dot = [&](int d) {
+            if (e == hipSuccess)
+                e = launch_multidot_packed(dev<DotJob>(L.dot[d]), dev<int>(L.bdot[d]), na, L.ndot[d], s);
+            if (e == hipSuccess)
+                e = launch_reduce_packed(dev<DotJob>(L.dot[d]), dev<int>(L.bred[d]), na, L.nred[d], s);
+        };
+        vec(kVPrep);
+        if (e == hipSuccess)
+            e = launch_rasm_packed(dev<RasmJob>(L.rasm), dev<int>(L.brasm), na, L.nrasm, s);
+        vec(kVUpd);
+        if (e == hipSuccess)
+            e = launch_matvec_lists_packed(dev<MatvecJob>(L.mv), dev<int>(L.bmv), na, L.nmv,
+                                           L.mv_threads, s);
+        vec(kVSub);
+        dot(0);
+        vec(kVAxpy1);
+        dot(1);
+        vec(kVAxpy2);
+        dot(2);
+        vec(kVScale);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_res, d_res, sizeof(EngResult) * cap, hipMemcpyDeviceToHost, s);
+        return e;
+    }
+
+    // the step's jobs of problem q (slot i) from its state
+    void fill(int i, EngProb& q) {
+        rbf_problem* p = q.p;
+        const long long n = p->n;
+        const int prec = (q.mixed && q.st == EngProb::kArnoldi) ? 1 : 0;   // the operator's precision
+        const int rprec = q.mixed ? 1 : 0;                                 // the preconditioner's
+        for (int v = 0; v < kVPhases; ++v) {
+            VecJob& J = host<VecJob>(L.vec[v])[i];
+            J = VecJob{};
+            J.op = VecJob::kNop;
+            J.n = n;
+        }
+        for (int d = 0; d < 3; ++d) {
+            DotJob& D = host<DotJob>(L.dot[d])[i];
+            D = DotJob{};
+            D.nb = q.nb_dot;
+            D.n = n;
+            D.partial = p->partial;
+        }
+        MatvecJob& M = host<MatvecJob>(L.mv)[i];
+        M = MatvecJob{};
+        M.a = p->mv_args();
+        M.a32 = p->mv32_args();
+        M.nl = p->nl;
+        M.skip = 1;
+        RasmJob& Rj = host<RasmJob>(L.rasm)[i];
+        Rj = RasmJob{};
+        Rj.a = p->pc_args();
+        Rj.Z = rprec ? static_cast<const void*>(p->Z32) : static_cast<const void*>(p->Z64);
+        Rj.prec = rprec;
+        Rj.skip = 1;
+        EngResult* res = d_res + q.slot;
+        double* res_n2 = &res->n2;
+        auto dotjob = [&](int d, const double* V, long long ldv, int nv, const double* w, double* out) {
+            DotJob& D = host<DotJob>(L.dot[d])[i];
+            D.V = V;
+            D.ldv = ldv;
+            D.nv = nv;
+            D.w = w;
+            D.out = out;
+        };
+        auto resid = [&]() {   // w = A x, r = f - w, <r, r>
+            M.skip = 0;
+            M.prec = 0;
+            M.w = p->x;
+            M.y = p->w;
+            VecJob& S = host<VecJob>(L.vec[kVSub])[i];
+            S.op = VecJob::kSub;
+            S.a = p->fs;
+            S.b = p->w;
+            S.y = p->r;
+            dotjob(0, p->r, 0, 1, p->r, res_n2);
+        };
+        switch (q.st) {
+            case EngProb::kInit: {
+                VecJob& F = host<VecJob>(L.vec[kVPrep])[i];
+                F.op = VecJob::kFill;
+                F.y = p->x;
+                dotjob(0, p->fs, 0, 1, p->fs, res_n2);
+                break;
+            }
+            case EngProb::kResid:
+                resid();
+                break;
+            case EngProb::kArnoldi: {
+                double* V = p->V;
+                double* vj = V + (long long)q.j * n;
+                if (q.start_cycle) {
+                    VecJob& P0 = host<VecJob>(L.vec[kVPrep])[i];
+                    P0.op = VecJob::kScaleByInv;
+                    P0.a = p->r;
+                    P0.den = res_n2;
+                    P0.y = V;
+                }
+                Rj.skip = 0;
+                Rj.v = vj;
+                Rj.z = p->z;
+                M.skip = 0;
+                M.prec = prec;
+                M.w = p->z;
+                M.y = p->w;
+                dotjob(0, V, n, q.j + 1, p->w, res->h1);
+                VecJob& A1 = host<VecJob>(L.vec[kVAxpy1])[i];
+                A1.op = VecJob::kMultiAxpy;
+                A1.a = V;
+                A1.ld = n;
+                A1.nv = q.j + 1;
+                A1.coef = res->h1;
+                A1.y = p->w;
+                A1.sign = -1.0;
+                dotjob(1, V, n, q.j + 1, p->w, res->h2);
+                VecJob& A2 = host<VecJob>(L.vec[kVAxpy2])[i];
+                A2 = A1;
+                A2.coef = res->h2;
+                dotjob(2, p->w, 0, 1, p->w, res_n2);
+                VecJob& Sc = host<VecJob>(L.vec[kVScale])[i];
+                Sc.op = VecJob::kScaleByInv;
+                Sc.a = p->w;
+                Sc.den = res_n2;
+                Sc.y = V + (long long)(q.j + 1) * n;
+                break;
+            }
+            case EngProb::kUpdate: {
+                double* coef = host<double>(L.coef) + 64 * i;
+                for (int t = 0; t < q.k; ++t) coef[t] = q.yv[t];
+                VecJob& P0 = host<VecJob>(L.vec[kVPrep])[i];
+                P0.op = VecJob::kMultiAxpy;
+                P0.a = p->V;
+                P0.ld = n;
+                P0.nv = q.k;
+                P0.coef = d_coef + 64 * i;
+                P0.y = p->w;
+                P0.sign = 1.0;
+                P0.overwrite = 1;
+                Rj.skip = 0;
+                Rj.v = p->w;
+                Rj.z = p->z;
+                VecJob& U = host<VecJob>(L.vec[kVUpd])[i];
+                U.op = VecJob::kAxpy;
+                U.a = p->z;
+                U.y = p->x;
+                resid();
+                break;
+            }
+        }
+    }
+
+    // the true residual's decision (solve_impl's loop head); false: the problem ended
+    bool decide(EngProb& q, std::vector<EngineDone>* done, double n2) {
+        rbf_problem* p = q.p;
+        q.rel = std::sqrt(n2) / q.bnorm;
+        p->history.push_back(q.rel);
+        rbf_status s = RBF_OK;
+        std::string msg;
+        if (!std::isfinite(q.rel)) {
+            s = RBF_ENAN;
+            msg = "non-finite residual";
+        } else if (q.rel <= q.o.rtol) {
+            s = RBF_OK;
+        } else if (!q.mixed && q.iters >= q.o.max_iters) {
+            s = RBF_ENOCONV;
+        } else if (q.mixed && (q.outer >= q.o.max_outer || q.iters >= q.o.max_iters)) {
+            s = RBF_ENOCONV;
+        } else {
+            // a new cycle: beta = ||r|| (the lone solve's norm of its copy of r)
+            const double beta = std::sqrt(n2);
+            q.tol_abs = q.mixed ? std::max(q.o.inner_rtol * (q.rel * q.bnorm), 0.5 * q.o.rtol * q.bnorm)
+                                : q.o.rtol * q.bnorm;
+            if (!std::isfinite(beta)) {
+                finish(q, done, RBF_ENAN, "non-finite residual");
+                return false;
+            }
+            if (beta <= q.tol_abs) {   // nothing to do in this cycle
+                if (q.mixed) {
+                    ++q.outer;
+                    q.st = EngProb::kResid;
+                    return true;
+                }
+                finish(q, done, RBF_ENOCONV, "residual estimate below tolerance, true residual above");
+                return false;
+            }
+            q.est = beta;
+            std::fill(q.H.begin(), q.H.end(), 0.0);
+            std::fill(q.gv.begin(), q.gv.end(), 0.0);
+            q.gv[0] = beta;
+            q.j = 0;
+            q.k = 0;
+            q.breakdown = false;
+            q.start_cycle = true;
+            q.st = EngProb::kArnoldi;
+            return true;
+        }
+        if (s == RBF_ENOCONV) {
+            char buf[160];
+            snprintf(buf, sizeof buf, q.mixed ? "no convergence in %d outer steps (rel. residual %.3e)"
+                                              : "no convergence in %d iterations (rel. residual %.3e)",
+                     q.mixed ? q.outer : q.iters, q.rel);
+            msg = buf;
+        }
+        finish(q, done, s, msg);
+        return false;
+    }
+
+    void finish(EngProb& q, std::vector<EngineDone>* done, rbf_status s, const std::string& msg) {
+        rbf_problem* p = q.p;
+        hipError_t e = launch_unpermute(p->x, p->perm, p->n, q.lam_out, st);
+        if (e == hipSuccess && !p->lam) {
+            if (p->alloc_n(&p->lam, p->n) != RBF_OK) e = hipErrorOutOfMemory;
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->lam, p->x, sizeof(double) * p->n, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess && s == RBF_OK) s = RBF_EDEVICE;
+        p->solved = s == RBF_OK;
+        // the information a lone solve reports (phase times are not per problem here)
+        p->last_info = rbf_solve_info{};
+        rbf_solve_info& info = p->last_info;
+        info.iterations = q.iters;
+        info.outer_iterations = q.outer;
+        info.restarts = q.cycles;
+        info.rel_residual = q.rel;
+        info.t_init = p->t_init;
+        info.t_pcsetup = q.mixed ? p->t_pcsetup32 : p->t_pcsetup64;
+        info.interactions_per_matvec = p->interactions;
+        info.matvecs64 = q.mv64;
+        info.matvecs32 = q.mv32;
+        info.precond_applies = q.pc;
+        info.device_bytes = p->bytes;
+        info.shifted_blocks = q.mixed ? p->shifted_blocks32 : 0;
+        p->mark(st);
+        done->push_back(EngineDone{q.tag, s, e != hipSuccess ? hipGetErrorString(e) : msg});
+        free_slots.push_back(q.slot);
+        q.p = nullptr;   // ended
+    }
+
+    // after the step: read each problem's results and advance its state
+    void advance(std::vector<EngineDone>* done) {
+        for (size_t i = 0; i < act.size(); ++i) {
+            EngProb& q = act[i];
+            const EngResult& r = h_res[q.slot];
+            switch (q.st) {
+                case EngProb::kInit: {
+                    q.bnorm = std::sqrt(r.n2);
+                    q.p->history.clear();
+                    if (q.bnorm == 0.0) {
+                        q.rel = 0.0;
+                        finish(q, done, RBF_OK, "");
+                    } else {
+                        q.st = EngProb::kResid;
+                    }
+                    break;
+                }
+                case EngProb::kResid:
+                    q.mv64 += 1;
+                    decide(q, done, r.n2);
+                    break;
+                case EngProb::kArnoldi: {
+                    q.start_cycle = false;
+                    q.pc += 1;
+                    (q.mixed ? q.mv32 : q.mv64) += 1;
+                    const int m = q.m, j = q.j;
+                    std::vector<double>& H = q.H;
+                    for (int t = 0; t <= j; ++t) H[(size_t)t * m + j] = r.h1[t] + r.h2[t];
+                    const double hn = std::sqrt(r.n2);
+                    H[(size_t)(j + 1) * m + j] = hn;
+                    for (int t = 0; t < j; ++t) {
+                        const double a = H[(size_t)t * m + j], bb = H[(size_t)(t + 1) * m + j];
+                        H[(size_t)t * m + j] = q.cs[t] * a + q.sn[t] * bb;
+                        H[(size_t)(t + 1) * m + j] = -q.sn[t] * a + q.cs[t] * bb;
+                    }
+                    const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+                    const double rho = std::hypot(a, bb);
+                    if (!std::isfinite(rho)) {
+                        finish(q, done, RBF_ENAN, "non-finite Hessenberg entry");
+                        break;
+                    }
+                    q.cs[j] = rho > 0 ? a / rho : 1.0;
+                    q.sn[j] = rho > 0 ? bb / rho : 0.0;
+                    H[(size_t)j * m + j] = rho;
+                    H[(size_t)(j + 1) * m + j] = 0.0;
+                    q.gv[j + 1] = -q.sn[j] * q.gv[j];
+                    q.gv[j] = q.cs[j] * q.gv[j];
+                    ++q.iters;
+                    q.k = j + 1;
+                    q.est = std::fabs(q.gv[j + 1]);
+                    bool stop = false;
+                    if (hn == 0.0) {
+                        q.breakdown = true;
+                        stop = true;
+                    }
+                    if (q.est <= q.tol_abs || q.iters >= q.o.max_iters) stop = true;
+                    if (stop || j + 1 == m) {
+                        // y = H^{-1} g for the cycle's end, next step
+                        for (int t = q.k - 1; t >= 0; --t) {
+                            double sacc = q.gv[t];
+                            for (int jj = t + 1; jj < q.k; ++jj) sacc -= H[(size_t)t * m + jj] * q.yv[jj];
+                            q.yv[t] = sacc / H[(size_t)t * m + t];
+                        }
+                        q.st = EngProb::kUpdate;
+                    } else {
+                        q.j = j + 1;
+                    }
+                    break;
+                }
+                case EngProb::kUpdate: {
+                    q.pc += 1;
+                    q.mv64 += 1;
+                    ++q.cycles;
+                    if (q.mixed) {
+                        ++q.outer;
+                        decide(q, done, r.n2);
+                    } else if (q.breakdown) {
+                        q.rel = std::sqrt(r.n2) / q.bnorm;
+                        q.p->history.push_back(q.rel);
+                        if (q.rel > q.o.rtol) {
+                            char buf[96];
+                            snprintf(buf, sizeof buf, "Arnoldi breakdown at residual %.3e", q.rel);
+                            finish(q, done, RBF_EBREAKDOWN, buf);
+                        } else {
+                            finish(q, done, RBF_OK, "");
+                        }
+                    } else {
+                        decide(q, done, r.n2);
+                    }
+                    break;
+                }
+            }
+        }
+        // drop the problems that ended
+        std::vector<EngProb> keep;
+        for (EngProb& q : act)
+            if (q.p) keep.push_back(std::move(q));
+        if (keep.size() != act.size()) layout_valid = false;
+        act.swap(keep);
+    }
+
+    rbf_status step(std::vector<EngineDone>* done) {
+        if (!joining.empty()) {
+            for (EngProb& q : joining) act.push_back(std::move(q));
+            joining.clear();
+            layout_valid = false;
+        }
+        if (act.empty()) return RBF_OK;
+        if (!layout_valid) {
+            if (gexec) {
+                (void)hipGraphExecDestroy(gexec);
+                gexec = nullptr;
+            }
+            HIP_TRY(plan());
+        }
+        for (size_t i = 0; i < act.size(); ++i) fill((int)i, act[i]);
+        if (use_graphs && !gexec) {
+            hipGraph_t g = nullptr;
+            hipStream_t cs = nullptr;
+            bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+            if (ok) ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                const hipError_t le = enqueue(cs);
+                const hipError_t ce = hipStreamEndCapture(cs, &g);
+                ok = le == hipSuccess && ce == hipSuccess && g != nullptr;
+            }
+            if (ok) ok = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (cs) (void)hipStreamDestroy(cs);
+            (void)hipGetLastError();
+            if (!ok) {
+                if (gexec) (void)hipGraphExecDestroy(gexec);
+                gexec = nullptr;
+                use_graphs = false;   // launch one by one from now on
+            }
+        }
+        if (gexec)
+            HIP_TRY(hipGraphLaunch(gexec, st));
+        else
+            HIP_TRY(enqueue(st));
+        HIP_TRY(hipEventRecord(ev_done, st));
+        HIP_TRY(hipEventSynchronize(ev_done));
+        advance(done);
+        return RBF_OK;
+    }
+};
+
+Engine* engine_create(hipStream_t st, int capacity, bool graphs) {
+    Engine* e = new (std::nothrow) Engine();
+    if (!e) return nullptr;
+    e->st = st;
+    e->cap = std::max(1, std::min(capacity, 64));
+    e->use_graphs = graphs;
+    for (int k = e->cap - 1; k >= 0; --k) e->free_slots.push_back(k);
+    if (hipMalloc(reinterpret_cast<void**>(&e->d_res), sizeof(EngResult) * e->cap) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&e->h_res), sizeof(EngResult) * e->cap) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev_done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        delete e;
+        return nullptr;
+    }
+    return e;
+}
+
+void engine_destroy(Engine* e) { delete e; }
+
+int engine_active(const Engine* e) { return (int)(e->act.size() + e->joining.size()); }
+
+rbf_status engine_add(Engine* e, rbf_problem* p, const rbf_solve_opts& o, double* d_lam_out,
+                      void* tag) {
+    if (engine_active(e) >= e->cap) return fail(RBF_ELIMIT, "the engine is full");
+    if (p->nl.nunits == 0) return fail(RBF_ELIMIT, "the problem has no neighbour lists");
+    if (o.restart < 1 || o.restart > 63) return fail(RBF_EINVAL, "restart must be in [1, 63]");
+    if (!p->have_values) return fail(RBF_ESTATE, "no right-hand side");
+    const bool mixed = o.precision == RBF_MIXED;
+    if (mixed ? !p->Z32 : !p->Z64) return fail(RBF_ESTATE, "the preconditioner is not built");
+    RBF_TRY(ensure_workspace(p, o.restart, e->st));
+    EngProb q;
+    q.p = p;
+    q.o = o;
+    q.lam_out = d_lam_out;
+    q.tag = tag;
+    q.mixed = mixed;
+    q.m = o.restart;
+    q.H.assign((size_t)(q.m + 1) * q.m, 0.0);
+    q.cs.assign(q.m, 0.0);
+    q.sn.assign(q.m, 0.0);
+    q.gv.assign(q.m + 1, 0.0);
+    q.yv.assign(q.m, 0.0);
+    q.nb_vec = vec_blocks(p->n);
+    q.nb_dot = dot_blocks(p->n);
+    q.ngroups = p->nl.ngroups;
+    q.nsub = (int)p->nsub;
+    q.slot = e->free_slots.back();
+    e->free_slots.pop_back();
+    p->history.clear();
+    e->joining.push_back(std::move(q));
+    return RBF_OK;
+}
+
+rbf_status engine_step(Engine* e, std::vector<EngineDone>* done) {
+    try {
+        return e->step(done);
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in the packed engine");
+    }
+}
+
+void engine_info(const rbf_problem* p, rbf_solve_info* info) {
+    if (info) *info = p->last_info;
+}
+
+}  // namespace rbf
 
 extern "C" {
 
@@ -1460,6 +2078,24 @@ rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, lo
         return evaluate_impl(p, d_targets, m, d_out, as_stream(stream));
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_evaluate_device");
+    }
+}
+
+rbf_status rbf_target_counts_device(const rbf_problem* p, const double* d_targets, long long m,
+                                    int* d_counts, void* stream) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    if (m < 0 || (m > 0 && (!d_targets || !d_counts))) return fail(RBF_EINVAL, "bad targets");
+    if (m == 0) return RBF_OK;
+    try {
+        MarkOnExit mk{p, as_stream(stream)};
+        double* scratch_out;
+        rbf_problem* q = const_cast<rbf_problem*>(p);
+        RBF_TRY(q->alloc_n(&scratch_out, m));
+        rbf_status s = evaluate_impl(p, d_targets, m, scratch_out, as_stream(stream), d_counts);
+        q->release(scratch_out, as_stream(stream));
+        return s;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_target_counts_device");
     }
 }
 

@@ -139,7 +139,143 @@ inline unsigned stream_grid(long long n) {
     return (unsigned)b;
 }
 
+// ---- packed forms: one launch serves the jobs of many problems --------------
+// Job j owns workgroups [block0_j, block0_{j+1}); a workgroup finds its job by
+// a binary search over the block offsets and runs the single-problem loop with
+// its own block index and block count, so every job computes exactly what the
+// single-problem launch computes (the same grid-stride decomposition, hence
+// bit-identical reductions).
+__device__ __forceinline__ int find_job(const int* __restrict__ block0, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (block0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_vec_packed(const VecJob* __restrict__ jobs,
+                                                       const int* __restrict__ block0, int njobs) {
+    const int j = find_job(block0, njobs, blockIdx.x);
+    const VecJob& J = jobs[j];
+    const long long nb = block0[j + 1] - block0[j], b = blockIdx.x - block0[j];
+    const long long n = J.n;
+    const int op = J.op;
+    const double* __restrict__ A = J.a;
+    double* __restrict__ Y = J.y;
+    if (op == VecJob::kNop) return;
+    if (op == VecJob::kMultiAxpy) {
+        __shared__ double hs[64];
+        const int nv = J.nv;
+        const long long ld = J.ld;
+        if (threadIdx.x < nv) hs[threadIdx.x] = J.coef[threadIdx.x];
+        __syncthreads();
+        const double sign = J.sign;
+        const bool over = J.overwrite != 0;
+        for (long long i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+            double s = 0.0;
+            for (int k = 0; k < nv; ++k) s = __builtin_fma(hs[k], A[k * ld + i], s);
+            Y[i] = __builtin_fma(sign, s, over ? 0.0 : Y[i]);
+        }
+        return;
+    }
+    const double* __restrict__ Bv = J.b;
+    const double d = op == VecJob::kScaleByInv ? __builtin_sqrt(J.den[0]) : 1.0;
+    for (long long i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+        if (op == VecJob::kSub) Y[i] = A[i] - Bv[i];
+        else if (op == VecJob::kAxpy) Y[i] = __builtin_fma(1.0, A[i], Y[i]);
+        else if (op == VecJob::kFill) Y[i] = 0.0;
+        else if (op == VecJob::kScaleByInv) Y[i] = A[i] / d;
+    }
+}
+
+// out partials of <V_k, w>, k < nv, in chunks of 8 as the single-problem
+// launches take them (partial[k * kDotBlocks + b])
+__global__ __launch_bounds__(kBlock) void k_multidot_packed(const DotJob* __restrict__ jobs,
+                                                            const int* __restrict__ block0,
+                                                            int njobs) {
+    const int j = find_job(block0, njobs, blockIdx.x);
+    const DotJob J = jobs[j];   // a few pointers and sizes
+    const long long nb = block0[j + 1] - block0[j], b = blockIdx.x - block0[j];
+    __shared__ double sh[kBlock / 64][kDotChunk];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k0 = 0; k0 < J.nv; k0 += kDotChunk) {
+        const int c = J.nv - k0 < kDotChunk ? J.nv - k0 : kDotChunk;
+        const double* Vk = J.V + (long long)k0 * J.ldv;
+        double acc[kDotChunk];
+#pragma unroll
+        for (int k = 0; k < kDotChunk; ++k) acc[k] = 0.0;
+        for (long long i = b * kBlock + threadIdx.x; i < J.n; i += nb * kBlock) {
+            const double wi = J.w[i];
+#pragma unroll
+            for (int k = 0; k < kDotChunk; ++k)
+                if (k < c) acc[k] = __builtin_fma(Vk[k * J.ldv + i], wi, acc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kDotChunk; ++k) {
+            const double v = wave_sum(acc[k]);
+            if (lane == 0) sh[wave][k] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < c) {
+            double v = 0.0;
+            for (int q = 0; q < kBlock / 64; ++q) v += sh[q][threadIdx.x];
+            J.partial[(long long)(k0 + threadIdx.x) * kDotBlocks + b] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// out[k] = sum of the nb partials of k, one workgroup per (job, k), as
+// k_reduce_partials
+__global__ __launch_bounds__(kBlock) void k_reduce_packed(const DotJob* __restrict__ jobs,
+                                                          const int* __restrict__ block0,
+                                                          int njobs) {
+    const int j = find_job(block0, njobs, blockIdx.x);
+    const DotJob J = jobs[j];
+    const int k = blockIdx.x - block0[j];
+    if (k >= J.nv) return;
+    __shared__ double sh[kBlock];
+    const double* p = J.partial + (long long)k * kDotBlocks;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < J.nb; b += kBlock) v += p[b];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) J.out[k] = sh[0];
+}
+
 }  // namespace
+
+int dot_blocks(long long n) {
+    long long nb64 = (n + kBlock - 1) / kBlock;
+    int nb = (int)(nb64 < kDotBlocks ? nb64 : kDotBlocks);
+    return nb < 1 ? 1 : nb;
+}
+
+int vec_blocks(long long n) { return (int)stream_grid(n); }
+
+hipError_t launch_vec_packed(const VecJob* jobs, const int* block0, int njobs, int nblocks,
+                             hipStream_t st) {
+    if (njobs > 0 && nblocks > 0) k_vec_packed<<<nblocks, kBlock, 0, st>>>(jobs, block0, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_multidot_packed(const DotJob* jobs, const int* block0, int njobs, int nblocks,
+                                  hipStream_t st) {
+    if (njobs > 0 && nblocks > 0) k_multidot_packed<<<nblocks, kBlock, 0, st>>>(jobs, block0, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_packed(const DotJob* jobs, const int* block0, int njobs, int nblocks,
+                                hipStream_t st) {
+    if (njobs > 0 && nblocks > 0) k_reduce_packed<<<nblocks, kBlock, 0, st>>>(jobs, block0, njobs);
+    return hipGetLastError();
+}
 
 hipError_t launch_multidot(const double* V, long long ldv, int nv, const double* w, long long n,
                            double* partial, double* out, hipStream_t st) {

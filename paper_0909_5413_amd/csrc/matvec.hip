@@ -293,12 +293,12 @@ constexpr int kW32Base = 8 * (kGroupSpan + 1);
 // workgroup per group, one wave per unit; the null source (weight 0) sits at
 // the middle of the group; four list entries per 8-byte load, loaded two loop
 // passes ahead.
-__global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec64_lists(MatvecArgs a,
-                                                                       NeighborLists nl,
-                                                                       const double* __restrict__ w,
-                                                                       double* __restrict__ y) {
-    __shared__ __attribute__((aligned(16))) char lds[kXYBase + 16 * (kGroupSpan + 1) + 256];
-    const GroupView gr = load_group(nl.group, blockIdx.x);
+constexpr int kMv64Lds = kXYBase + 16 * (kGroupSpan + 1) + 256;
+
+__device__ __forceinline__ void mv64_lists_group(MatvecArgs a, NeighborLists nl,
+                                                 const double* __restrict__ w,
+                                                 double* __restrict__ y, int gi, char* lds) {
+    const GroupView gr = load_group(nl.group, gi);
     const int tid = threadIdx.x, lane = tid & 63, wv = uniform(tid >> 6);
     const Rows r = span_rows(a.scell, a.g, gr.cy, gr.cxa, gr.cxb);
     const int n = r.n;
@@ -358,16 +358,24 @@ __global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec64_lists(MatvecAr
     if (act) y[t] = (acc0 + acc1) * a.norm;
 }
 
+__global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec64_lists(MatvecArgs a,
+                                                                       NeighborLists nl,
+                                                                       const double* __restrict__ w,
+                                                                       double* __restrict__ y) {
+    __shared__ __attribute__((aligned(16))) char lds[kMv64Lds];
+    mv64_lists_group(a, nl, w, y, blockIdx.x, lds);
+}
+
 // FP32 form: the group's sources are staged in one frame centred on the group
 // (scaled coordinates: the cell-centre-relative FP32 ones plus the cell offset,
 // summed in FP64 and rounded once), so d2 is the negated base-2 exponent;
 // Kahan-compensated FP32 accumulation, FP64 output.
-__global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec32_lists(Matvec32Args a,
-                                                                       NeighborLists nl,
-                                                                       const double* __restrict__ w,
-                                                                       double* __restrict__ y) {
-    __shared__ __attribute__((aligned(16))) char lds[kW32Base + 4 * (kGroupSpan + 1)];
-    const GroupView gr = load_group(nl.group, blockIdx.x);
+constexpr int kMv32Lds = kW32Base + 4 * (kGroupSpan + 1);
+
+__device__ __forceinline__ void mv32_lists_group(Matvec32Args a, NeighborLists nl,
+                                                 const double* __restrict__ w,
+                                                 double* __restrict__ y, int gi, char* lds) {
+    const GroupView gr = load_group(nl.group, gi);
     const int tid = threadIdx.x, lane = tid & 63, wv = uniform(tid >> 6);
     const Rows r = span_rows(a.scell, a.g, gr.cy, gr.cxa, gr.cxb);
     const int n = r.n;
@@ -433,6 +441,40 @@ __global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec32_lists(Matvec32
     if (act) y[t] = acc.value() * a.norm;
 }
 
+__global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec32_lists(Matvec32Args a,
+                                                                       NeighborLists nl,
+                                                                       const double* __restrict__ w,
+                                                                       double* __restrict__ y) {
+    __shared__ __attribute__((aligned(16))) char lds[kMv32Lds];
+    mv32_lists_group(a, nl, w, y, blockIdx.x, lds);
+}
+
+// Packed form: workgroup b serves group b - block0[j] of job j (FP64 or FP32
+// lists by the job), with the staging sized for the FP64 form.
+__device__ __forceinline__ int find_job_mv(const int* __restrict__ block0, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (block0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(64 * kGroupMaxUnits) void k_matvec_lists_packed(
+    const MatvecJob* __restrict__ jobs, const int* __restrict__ block0, int njobs) {
+    static_assert(kMv64Lds >= kMv32Lds, "the FP64 staging is the larger");
+    __shared__ __attribute__((aligned(16))) char lds[kMv64Lds];
+    const int j = uniform(find_job_mv(block0, njobs, blockIdx.x));
+    const MatvecJob& J = jobs[j];
+    const int gi = blockIdx.x - block0[j];
+    if (J.skip) return;
+    if (J.prec == 0)
+        mv64_lists_group(J.a, J.nl, J.w, J.y, gi, lds);
+    else
+        mv32_lists_group(J.a32, J.nl, J.w, J.y, gi, lds);
+}
+
 inline unsigned mv_grid(long long ncells) {
     long long b = (ncells + kMvWaves - 1) / kMvWaves;
     return (unsigned)(b < 2048 ? (b > 0 ? b : 1) : 2048);
@@ -490,6 +532,13 @@ hipError_t launch_list_fill(const MatvecArgs& a, const NeighborLists& nl, unsign
 hipError_t launch_matvec64_lists(const MatvecArgs& a, const NeighborLists& nl, const double* w,
                                  double* y, hipStream_t st) {
     if (nl.ngroups > 0) k_matvec64_lists<<<nl.ngroups, 64 * nl.gunits, 0, st>>>(a, nl, w, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec_lists_packed(const MatvecJob* jobs, const int* block0, int njobs,
+                                      int nblocks, int threads, hipStream_t st) {
+    if (njobs > 0 && nblocks > 0)
+        k_matvec_lists_packed<<<nblocks, threads, 0, st>>>(jobs, block0, njobs);
     return hipGetLastError();
 }
 

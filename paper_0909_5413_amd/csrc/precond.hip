@@ -1321,14 +1321,22 @@ __device__ __forceinline__ double row_dot(const T* __restrict__ zr, const T* vs,
     }
 }
 
+struct RasmLds {
+    double vs[RBF_MAX_BLOCK];   // the member values (as T)
+    int rb[kMaxRanges], re[kMaxRanges];
+    int nr_s, n_omega_s, n_c_s;
+};
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T* __restrict__ Z,
-                                                         const double* __restrict__ v,
-                                                         double* __restrict__ z) {
-    __shared__ T vs[RBF_MAX_BLOCK];
-    __shared__ int rb[kMaxRanges], re[kMaxRanges];
-    __shared__ int nr_s, n_omega_s, n_c_s;
-    const long long c = blockIdx.x;
+__device__ __forceinline__ void rasm_cell(PrecondArgs a, const T* __restrict__ Z,
+                                          const double* __restrict__ v, double* __restrict__ z,
+                                          long long c, RasmLds& L) {
+    T* vs = reinterpret_cast<T*>(L.vs);
+    int* rb = L.rb;
+    int* re = L.re;
+    int& nr_s = L.nr_s;
+    int& n_omega_s = L.n_omega_s;
+    int& n_c_s = L.n_c_s;
     const int tid = threadIdx.x;
     if (tid == 0) {
         if (a.mem) {
@@ -1358,6 +1366,35 @@ __global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T*
         for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, RBF_WAVE);
         if (ph == 0 && r < n_c) z[mlist ? mlist[n_omega - n_c + r] : own + r] = sum;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T* __restrict__ Z,
+                                                         const double* __restrict__ v,
+                                                         double* __restrict__ z) {
+    __shared__ RasmLds L;
+    rasm_cell<T>(a, Z, v, z, blockIdx.x, L);
+}
+
+// Packed form: workgroup b serves subdomain b - block0[j] of job j.
+__global__ __launch_bounds__(kThreads) void k_rasm_packed(const RasmJob* __restrict__ jobs,
+                                                          const int* __restrict__ block0,
+                                                          int njobs) {
+    __shared__ RasmLds L;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (block0[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const int j = __builtin_amdgcn_readfirstlane(lo);
+    const RasmJob& J = jobs[j];
+    const long long c = (long long)blockIdx.x - block0[j];
+    if (J.skip) return;
+    if (J.prec == 0)
+        rasm_cell<double>(J.a, static_cast<const double*>(J.Z), J.v, J.z, c, L);
+    else
+        rasm_cell<float>(J.a, static_cast<const float*>(J.Z), J.v, J.z, c, L);
 }
 
 // Members of box b (one wave per box): the candidate cells are those of the
@@ -1437,6 +1474,12 @@ hipError_t launch_box_members(const PrecondArgs& a, const BoxGeometry& bg, int* 
         k_box_members<true><<<grid, kBoxThreads, 0, st>>>(a, bg, n_omega, n_own, moff, mem);
     else
         k_box_members<false><<<grid, kBoxThreads, 0, st>>>(a, bg, n_omega, n_own, moff, mem);
+    return hipGetLastError();
+}
+
+hipError_t launch_rasm_packed(const RasmJob* jobs, const int* block0, int njobs, int nblocks,
+                              hipStream_t st) {
+    if (njobs > 0 && nblocks > 0) k_rasm_packed<<<nblocks, kThreads, 0, st>>>(jobs, block0, njobs);
     return hipGetLastError();
 }
 

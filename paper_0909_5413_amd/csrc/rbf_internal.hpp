@@ -5,9 +5,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 struct rbf_problem;
+#include "../../include/rbf.h"
 
 namespace rbf {
 
@@ -238,6 +240,29 @@ constexpr long long kNoAllocMaxPoints = 1LL << 22;
 // doubles), looked up with hipGetSymbolAddress on the first call per device.
 hipError_t noalloc_scratch(int device, double** out);
 
+// ---- the packed solve engine (capi.cpp) --------------------------------------
+// Advances the GMRES solves of several problems together in packed launches
+// on one stream (see capi.cpp).  Not thread-safe: one thread drives an engine.
+class Engine;
+struct EngineDone {
+    void* tag;
+    rbf_status status;
+    std::string message;
+};
+Engine* engine_create(hipStream_t st, int capacity, bool graphs);
+void engine_destroy(Engine* e);
+// p's preconditioner of o.precision must be built; the weights go to d_lam_out
+// (device, original order) when the solve ends; the problem joins at the next
+// step.  RBF_ELIMIT when the engine is full or p cannot be packed (no lists).
+rbf_status engine_add(Engine* e, rbf_problem* p, const rbf_solve_opts& o, double* d_lam_out,
+                      void* tag);
+int engine_active(const Engine* e);
+// One step of every active problem; the problems that ended are appended to
+// done (their weights written, their stream work enqueued and finished).
+rbf_status engine_step(Engine* e, std::vector<EngineDone>* done);
+// The solve information of a problem that ended (as rbf_solve_device fills it).
+void engine_info(const rbf_problem* p, rbf_solve_info* info);
+
 // ---- Krylov vector operations (krylov.hip) -----------------------------------
 constexpr int kDotBlocks = 1024;
 // out[k] = <V_k, w> for k < nv (V column k at V + k*ldv), deterministic
@@ -261,5 +286,65 @@ hipError_t launch_check_finite(const double* x, long long n, int* flag, hipStrea
 // in-place block sum helpers used by the driver
 hipError_t launch_sum_counts(const int* nnb, long long n, long long* partial_out,
                              hipStream_t st);
+
+// ---- packed launches: the same operation for many problems at once ----------
+// Each launch takes a device table of jobs and the workgroup offsets of the
+// jobs (block0[j] .. block0[j + 1] serve job j, block0[njobs] = nblocks); a
+// job's workgroups run exactly the computation of the single-problem launch
+// (its block count is the single-problem grid), so results are bit-identical.
+// Blocks of the single-problem launches, for sizing the packed ones.
+int dot_blocks(long long n);   // launch_multidot's grid
+int vec_blocks(long long n);   // the element-wise kernels' grid
+struct VecJob {
+    enum : int { kSub = 0, kAxpy = 1, kFill = 2, kScaleByInv = 3, kMultiAxpy = 4, kNop = 5 };
+    int op;                  // y = a - b | y += a | y = 0 | y = a / sqrt(den[0]) |
+                             // y = sign * sum_k coef[k] a[k * ld ..] + (overwrite ? 0 : y) | none
+    int nv;                  // multi-axpy: vectors (<= 64)
+    int overwrite;
+    long long n, ld;
+    const double* a;
+    const double* b;
+    const double* den;
+    const double* coef;      // multi-axpy coefficients (device)
+    double* y;
+    double sign;
+};
+struct DotJob {              // out[k] = <V_k, w>, k < nv, partials in partial (nv = 0: none)
+    const double* V;
+    long long ldv;
+    int nv, nb;              // nb: dot_blocks(n)
+    const double* w;
+    long long n;
+    double* partial;         // kDotBlocks * nv
+    double* out;
+};
+hipError_t launch_vec_packed(const VecJob* jobs, const int* block0, int njobs, int nblocks,
+                             hipStream_t st);
+// partials of every DotJob (block counts nb each), then their sums (nv blocks each)
+hipError_t launch_multidot_packed(const DotJob* jobs, const int* block0, int njobs, int nblocks,
+                                  hipStream_t st);
+hipError_t launch_reduce_packed(const DotJob* jobs, const int* block0, int njobs, int nblocks,
+                                hipStream_t st);
+struct MatvecJob {           // y = A w by the lists (prec 0: FP64, 1: FP32)
+    MatvecArgs a;
+    Matvec32Args a32;
+    NeighborLists nl;
+    const double* w;
+    double* y;
+    int prec, skip;
+};
+// workgroups: nl.ngroups per job; threads: 64 * the largest nl.gunits
+hipError_t launch_matvec_lists_packed(const MatvecJob* jobs, const int* block0, int njobs,
+                                      int nblocks, int threads, hipStream_t st);
+struct RasmJob {             // z = M^-1 v (prec 0: FP64 Z, 1: FP32 Z)
+    PrecondArgs a;
+    const void* Z;
+    const double* v;
+    double* z;
+    int prec, skip;
+};
+// workgroups: a.ncells per job
+hipError_t launch_rasm_packed(const RasmJob* jobs, const int* block0, int njobs, int nblocks,
+                              hipStream_t st);
 
 }  // namespace rbf

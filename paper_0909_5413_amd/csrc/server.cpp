@@ -84,20 +84,160 @@ size_t predict_bytes(const double* pts, long long n, double cutoff, int overlap,
 
 }  // namespace
 
+// A prepared request on its way to the packed engine: its handle (set up and
+// factored) and its staging buffers.
+struct Prepared {
+    Request* r = nullptr;
+    rbf_problem* h = nullptr;
+    void *b_pts = nullptr, *b_vals = nullptr, *b_lam = nullptr;
+    size_t g_pts = 0, g_vals = 0, g_lam = 0;
+};
+
 struct rbf_server {
     rbf_server_opts opts{};
     int device = 0;
     size_t budget = 0;
     std::mutex mu;
-    std::condition_variable cv_sched, cv_done;
+    std::condition_variable cv_sched, cv_done, cv_engine;
     std::deque<Request*> queue, ready;
+    std::deque<Prepared> prepared;    // packed: set up, waiting to join the engine
     std::map<long long, std::unique_ptr<Request>> reqs;
     int active = 0;
     size_t used = 0;
     long long next_id = 0, finished = 0;
     bool stopping = false;
+    int workers_left = 0;
     std::thread dispatcher;
-    std::vector<std::thread> workers;
+    std::vector<std::thread> workers, engines;
+    std::vector<int> engine_load;      // solves each engine is running
+
+    // a request's end: its result recorded, its slot and budget freed
+    void complete(Request* r, rbf_status s, const std::string& msg, const rbf_solve_info& info) {
+        std::lock_guard<std::mutex> lk(mu);
+        r->status = s;
+        r->message = s == RBF_OK ? std::string() : msg;
+        r->info = info;
+        r->info.history = nullptr;
+        r->info.history_len = 0;
+        r->t_done = clk::now();
+        r->done = true;
+        r->pts.clear();
+        r->pts.shrink_to_fit();
+        r->vals.clear();
+        r->vals.shrink_to_fit();
+        --active;
+        used -= r->predicted;
+        ++finished;
+        cv_sched.notify_all();
+        cv_done.notify_all();
+    }
+
+    // The packed engine's thread: prepared requests join at step boundaries,
+    // every active solve advances one step per engine step, ended ones are
+    // copied out and released.
+    // Several engines (each a thread and a stream) share the prepared requests,
+    // each taking new ones only while it runs no more than any other: while one
+    // engine's host reads its step's results and updates its recurrences, the
+    // others' steps keep the device busy.
+    void engine_loop(int id) {
+        (void)hipSetDevice(device);
+        hipStream_t st = nullptr;
+        if (hipStreamCreate(&st) != hipSuccess) st = nullptr;
+        rbf::Engine* eng = st ? rbf::engine_create(st, opts.max_active, opts.graphs != 0) : nullptr;
+        std::map<void*, Prepared> running;
+        std::vector<rbf::EngineDone> done;
+        for (;;) {
+            std::deque<Prepared> joining;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                auto least = [&] {
+                    for (int l : engine_load)
+                        if (l < engine_load[id]) return false;
+                    return true;
+                };
+                cv_engine.wait(lk, [&] {
+                    return (!prepared.empty() && least()) || !running.empty() ||
+                           (stopping && workers_left == 0);
+                });
+                if (prepared.empty() && running.empty()) break;
+                while (!prepared.empty() && least()) {
+                    joining.push_back(prepared.front());
+                    prepared.pop_front();
+                    ++engine_load[id];
+                }
+            }
+            for (Prepared& pr : joining) {
+                rbf_solve_opts o = pr.r->opts;
+                o.stream = st;
+                rbf_status s = eng ? rbf::engine_add(eng, pr.h, o, static_cast<double*>(pr.b_lam), pr.r)
+                                   : RBF_EDEVICE;
+                if (s == RBF_OK) {
+                    running[pr.r] = pr;
+                } else {   // cannot be packed (no lists, or no engine): solve it alone here
+                    rbf_solve_info info{};
+                    s = rbf_solve_device(pr.h, &o, nullptr, static_cast<double*>(pr.b_lam), &info);
+                    const std::string msg = s == RBF_OK ? std::string() : std::string("solve: ") + rbf_last_error();
+                    finish(pr, st, s, msg, info);
+                    unload(id);
+                }
+            }
+            if (running.empty()) continue;
+            done.clear();
+            const rbf_status es = rbf::engine_step(eng, &done);
+            if (es != RBF_OK) {   // a device error: every running request fails
+                const std::string msg = std::string("engine: ") + rbf_last_error();
+                for (auto& kv : running) {
+                    finish(kv.second, st, es, msg, rbf_solve_info{});
+                    unload(id);
+                }
+                running.clear();
+                rbf::engine_destroy(eng);
+                eng = rbf::engine_create(st, opts.max_active, false);
+                continue;
+            }
+            for (const rbf::EngineDone& d : done) {
+                auto it = running.find(d.tag);
+                if (it == running.end()) continue;
+                rbf_solve_info info{};
+                rbf::engine_info(it->second.h, &info);
+                finish(it->second, st, d.status,
+                       d.status == RBF_OK ? std::string() : std::string("solve: ") + d.message, info);
+                running.erase(it);
+                unload(id);
+            }
+        }
+        if (eng) rbf::engine_destroy(eng);
+        if (st) (void)hipStreamDestroy(st);
+    }
+
+    void unload(int id) {
+        std::lock_guard<std::mutex> lk(mu);
+        --engine_load[id];
+        cv_engine.notify_all();
+    }
+
+    // copy out, release, complete (weights also on RBF_ENOCONV)
+    void finish(Prepared& pr, hipStream_t st, rbf_status s, const std::string& msg,
+                const rbf_solve_info& info) {
+        Request* r = pr.r;
+        const size_t nb = sizeof(double) * (size_t)r->n;
+        rbf_status out = s;
+        std::string m = msg;
+        if (s == RBF_OK || s == RBF_ENOCONV) {
+            r->lambda.resize(r->n);
+            hipError_t e = hipMemcpyAsync(r->lambda.data(), pr.b_lam, nb, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                out = RBF_EDEVICE;
+                m = std::string("copy-out: ") + hipGetErrorString(e);
+            }
+        }
+        rbf_destroy(pr.h);
+        if (pr.b_pts) rbf::cached_free(device, pr.b_pts, pr.g_pts, st);
+        if (pr.b_vals) rbf::cached_free(device, pr.b_vals, pr.g_vals, st);
+        if (pr.b_lam) rbf::cached_free(device, pr.b_lam, pr.g_lam, st);
+        complete(r, out, m, info);
+    }
 
     void dispatch_loop() {
         std::unique_lock<std::mutex> lk(mu);
@@ -148,6 +288,13 @@ struct rbf_server {
             s = rbf_precond_setup(h, r->opts.precision, st);
             if (s != RBF_OK) msg = std::string("preconditioner: ") + rbf_last_error();
         }
+        if (s == RBF_OK && opts.packed &&
+            (opts.pack_max_points == 0 || r->n <= opts.pack_max_points)) {   // an engine takes it
+            std::lock_guard<std::mutex> lk(mu);
+            prepared.push_back(Prepared{r, h, b_pts, b_vals, b_lam, g_pts, g_vals, g_lam});
+            cv_engine.notify_all();
+            return;
+        }
         rbf_solve_info info{};
         if (s == RBF_OK) {
             rbf_solve_opts o = r->opts;
@@ -162,27 +309,11 @@ struct rbf_server {
                 hip(hipStreamSynchronize(st)))
                 s = s2;
         }
-        info.history = nullptr;
-        info.history_len = 0;
         rbf_destroy(h);
         if (b_pts) rbf::cached_free(device, b_pts, g_pts, st);
         if (b_vals) rbf::cached_free(device, b_vals, g_vals, st);
         if (b_lam) rbf::cached_free(device, b_lam, g_lam, st);
-        std::lock_guard<std::mutex> lk(mu);
-        r->status = s;
-        r->message = s == RBF_OK ? std::string() : msg;
-        r->info = info;
-        r->t_done = clk::now();
-        r->done = true;
-        r->pts.clear();
-        r->pts.shrink_to_fit();
-        r->vals.clear();
-        r->vals.shrink_to_fit();
-        --active;
-        used -= r->predicted;
-        ++finished;
-        cv_sched.notify_all();
-        cv_done.notify_all();
+        complete(r, s, msg, info);
     }
 
     void worker_loop() {
@@ -199,6 +330,8 @@ struct rbf_server {
             run(r, st);
             lk.lock();
         }
+        --workers_left;
+        cv_engine.notify_all();
         lk.unlock();
         if (st) (void)hipStreamDestroy(st);
     }
@@ -210,6 +343,9 @@ void rbf_server_default_opts(rbf_server_opts* o) {
     if (!o) return;
     o->max_active = 8;
     o->max_device_bytes = 0;
+    o->packed = 2;
+    o->graphs = 1;
+    o->pack_max_points = 65536;
 }
 
 rbf_status rbf_server_create(const rbf_server_opts* opts, rbf_server** out) {
@@ -218,7 +354,8 @@ rbf_status rbf_server_create(const rbf_server_opts* opts, rbf_server** out) {
     rbf_server_opts o;
     rbf_server_default_opts(&o);
     if (opts) o = *opts;
-    if (o.max_active < 1 || o.max_active > 64) return RBF_EINVAL;
+    if (o.max_active < 1 || o.max_active > 64 || o.packed < 0 || o.packed > 8 ||
+        o.pack_max_points < 0) return RBF_EINVAL;
     rbf_server* s = new (std::nothrow) rbf_server();
     if (!s) return RBF_ENOMEM;
     s->opts = o;
@@ -232,8 +369,13 @@ rbf_status rbf_server_create(const rbf_server_opts* opts, rbf_server** out) {
         return RBF_EDEVICE;
     }
     s->budget = o.max_device_bytes ? o.max_device_bytes : (size_t)(0.9 * (double)free_b);
+    s->workers_left = o.max_active;
     s->dispatcher = std::thread([s] { s->dispatch_loop(); });
     for (int i = 0; i < o.max_active; ++i) s->workers.emplace_back([s] { s->worker_loop(); });
+    if (o.packed > 0) {
+        s->engine_load.assign(o.packed, 0);
+        for (int i = 0; i < o.packed; ++i) s->engines.emplace_back([s, i] { s->engine_loop(i); });
+    }
     *out = s;
     return RBF_OK;
 }
@@ -316,6 +458,12 @@ void rbf_server_destroy(rbf_server* s) {
         s->cv_sched.notify_all();
     }
     for (auto& t : s->workers)
+        if (t.joinable()) t.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->cv_engine.notify_all();
+    }
+    for (auto& t : s->engines)
         if (t.joinable()) t.join();
     delete s;
 }

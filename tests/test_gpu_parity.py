@@ -216,6 +216,15 @@ def test_evaluate_off_nodes(problems, name):
     err = np.abs(s - so)
     assert np.all(err <= 1e-13 * scale), float(np.max(err / np.where(scale > 0, scale, 1)))
     assert np.all(s[-nfar:] == 0.0) and np.all(so[-nfar:] == 0.0)
+    # the sources summed at each target, bit-exact (the staggered lattice too)
+    import torch
+    for t in (tg, W.staggered_lattice(int(round(np.sqrt(pts.shape[0]))))):
+        d_t = torch.tensor(t, device="cuda", dtype=torch.float64)
+        d_c = torch.empty(t.shape[0], device="cuda", dtype=torch.int32)
+        R.rbf_target_counts_device(h, d_t, t.shape[0], d_c, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        _, oc = P.evaluate(lam, t, with_counts=True)
+        assert np.array_equal(d_c.cpu().numpy(), oc)
 
 
 @pytest.mark.parametrize("name", ["mini", "ragged", "ill"])

@@ -1,8 +1,9 @@
 """The request loop (rbf_server_*) on the GPU, through the C ABI (-m gpu).
 
 Isolation: every request's weights from a mix of concurrent requests equal,
-bit for bit, the weights of the same request solved alone on a fresh handle
-(the server runs each request's launches unchanged on its own stream).
+bit for bit, the weights of the same request solved alone on a fresh handle,
+whether the server advances the solves together in packed launches (with or
+without the step captured as a graph) or runs each on its own stream.
 Admission: with a budget that fits about two requests the server still
 finishes every request, never charges more than the budget plus one request,
 and releases everything at the end.  A failing request does not disturb the
@@ -69,13 +70,24 @@ def oracle_judges(w, pts, f, lam, st):
     assert res <= gate, (w.name, res, gate)
 
 
-def test_mix_equals_alone(torch_dev):
+@pytest.mark.parametrize("packed,graphs,pmax", [(1, True, 0), (2, True, 0), (2, False, 0),
+                                                (2, True, 12000), (0, False, 0)])
+def test_mix_equals_alone(torch_dev, packed, graphs, pmax):
+    """Every request of a mix served concurrently equals, bit for bit, the
+    same request solved alone: with packed engines (every solve advanced in
+    shared launches, with and without the step captured as a graph, and with
+    the larger requests routed past the engines) and with one stream per
+    request."""
     reqs = mix(8, 777000)
     ref = []
     for w, pts, f, prec in reqs:
         say("alone", w.name, w.n, w.h_over_sigma, prec)
         ref.append(alone(w, pts, f, prec))
-    srv = R.rbf_server_create(max_active=4)
+    if pmax:
+        n = [w.n for w, _, _, _ in reqs]
+        assert min(n) <= pmax < max(n)
+    say("serving packed", packed, "graphs", graphs, "pack_max_points", pmax)
+    srv = R.rbf_server_create(max_active=4, packed=packed, graphs=graphs, pack_max_points=pmax)
     try:
         ids = [R.rbf_server_submit(srv, pts, f, w.sigma, w.cutoff, w.overlap,
                                    R.default_opts(rtol=w.rtol, precision=prec))
@@ -137,6 +149,45 @@ def test_admission_budget_and_failures(torch_dev):
         assert R.rbf_server_stats(srv)["bytes_charged"] == 0
     finally:
         R.rbf_server_destroy(srv)
+
+
+def test_packed_stream_of_uneven_requests(torch_dev):
+    """A longer stream through the packed engine: 24 requests of uneven size
+    and spacing (h/sigma down to 0.6, so some stop at the iteration cap),
+    FP64 and mixed, at most 6 on the device, arriving while others run: every
+    status, iteration count and weight vector equals the lone solve's."""
+    reqs = W.serving_requests(24, seed_base=555000, n_lo=1.5e3, n_hi=4e4)
+    data = []
+    for i, w in enumerate(reqs):
+        pts = w.points()
+        data.append((w, pts, w.values(pts), R.RBF_FP64 if i % 3 else R.RBF_MIXED))
+    srv = R.rbf_server_create(max_active=6)
+    try:
+        ids = []
+        for k, (w, pts, f, prec) in enumerate(data):
+            ids.append(R.rbf_server_submit(srv, pts, f, w.sigma, w.cutoff, w.overlap,
+                                           R.default_opts(rtol=w.rtol, precision=prec,
+                                                          max_iters=200)))
+            if k % 4 == 3:
+                time.sleep(0.01)
+        got = [R.rbf_server_wait(srv, rid, w.n, ok=(R.RBF_OK, R.RBF_ENOCONV))
+               for (w, _, _, _), rid in zip(data, ids)]
+    finally:
+        R.rbf_server_destroy(srv)
+    for (w, pts, f, prec), (lam, res, st) in zip(data, got):
+        h = R.rbf_setup(pts, f, w.sigma, w.cutoff, w.overlap)
+        try:
+            lam0, info0, st0 = R.rbf_solve(h, w.n, R.default_opts(rtol=w.rtol, precision=prec,
+                                                                   max_iters=200),
+                                           ok=(R.RBF_OK, R.RBF_ENOCONV))
+        finally:
+            R.rbf_destroy(h)
+        say("packed stream", w.name, w.n, round(w.h_over_sigma, 3), prec, R.status_name(st),
+            res.info.iterations, info0.iterations)
+        assert st == st0 and res.info.iterations == info0.iterations
+        assert res.info.outer_iterations == info0.outer_iterations
+        assert np.array_equal(lam, lam0)
+        oracle_judges(w, pts, f, lam, st)
 
 
 def test_block_cache_reuse_is_clean(torch_dev):

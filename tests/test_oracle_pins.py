@@ -333,9 +333,10 @@ def test_evaluate_matches_bruteforce(oracle_mod, n_side, ratio):
     P = oracle_mod.Problem(pts, w.sigma, w.cutoff)
     lam = W.random_weights(w.n, 42)
     tg, nfar = W.evaluation_targets(pts, w.cutoff)
-    s = P.evaluate(lam, tg)
+    s, cnt = P.evaluate(lam, tg, with_counts=True)
     ref, scale, mask = bruteforce_evaluate(pts, lam, tg, w.sigma, w.cutoff)
     assert np.all(np.abs(s - ref) <= 1e-14 * scale)
+    assert np.array_equal(cnt, mask.sum(axis=1))
     # the off-grid targets within the cutoff do see nodes, and clamping to the
     # border cell finds every one of them
     near = slice(len(tg) - nfar - 48, len(tg) - nfar)
