@@ -262,11 +262,26 @@ def geometry_run(R, torch, w, d_pts, d_f, d_lam, stream, sweep):
     return out
 
 
-def cpu_baseline(workload, n_side):
+def host_memory_gib():
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal:"):
+                    return int(line.split()[1]) / 2 ** 20
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(workload, n_side, targets=None):
+    """The oracle (setup with every local factor kept, FP64 GMRES(30) to the
+    workload's tolerance) on the workload itself, or on an n_side lattice of
+    the same spacing when n_side is smaller.  Returns the record, and on the
+    full workload also the oracle's weights and its interpolant at targets."""
     import numpy as np
     import oracle
     from paper_0909_5413_amd import workloads as W
-    w = W.sub_lattice(workload, n_side)
+    w = workload if (not n_side or n_side >= workload.n_side) else W.sub_lattice(workload, n_side)
     pts = w.points()
     f = w.values(pts)
     P = oracle.Problem(pts, w.sigma, w.cutoff, w.overlap)
@@ -279,14 +294,87 @@ def cpu_baseline(workload, n_side):
     x, info = P.gmres(f, 30, workload.rtol)
     dt = time.perf_counter() - t0
     matvecs = info.iterations + len(info.history)
-    return {
+    s = P.evaluate(x, targets) if (targets is not None and w is workload) else None
+    P.close()
+    rec = {
         "value": inter * matvecs / dt, "unit": "interactions/s",
         "cores": oracle.num_threads(), "kind": "oracle",
-        "sample": (f"oracle setup + FP64 GMRES(30) solve to {workload.rtol:g} on a "
-                   f"{n_side}x{n_side} jittered lattice (N={w.n}) with the same h/sigma, cutoff "
-                   f"and subdomain rule: {matvecs} matvecs x {inter} interactions in {dt:.2f} s"),
-        "seconds": dt, "iterations": info.iterations,
+        "sample": (f"oracle setup (every local Cholesky factor kept) + FP64 GMRES(30) solve to "
+                   f"{workload.rtol:g} on {'the workload itself' if w is workload else 'a sample'}:"
+                   f" {w.n_side}x{w.n_side} jittered lattice (N={w.n}), {matvecs} matvecs x "
+                   f"{inter} interactions in {dt:.2f} s"),
+        "seconds": dt, "iterations": info.iterations, "rel_residual": info.rel_residual,
+        "host_memory_gib": host_memory_gib(),
     }
+    return rec, (x if w is workload else None), s
+
+
+def oracle_matvec_1thread(names):
+    """One oracle matvec per workload on one thread (w ~ U(-1, 1))."""
+    import numpy as np
+    import oracle
+    from paper_0909_5413_amd import workloads as W
+    threads = oracle.num_threads()
+    out = {}
+    oracle.set_num_threads(1)
+    try:
+        for name in names:
+            w = W.WORKLOADS[name]
+            pts = w.points()
+            P = oracle.Problem(pts, w.sigma, w.cutoff, w.overlap)
+            wv = W.random_weights(w.n, W.SEED_BASE + 11)
+            t0 = time.perf_counter()
+            _, nnb = P.matvec(wv, with_counts=True)
+            dt = time.perf_counter() - t0
+            P.close()
+            out[name] = {"seconds": dt, "interactions_per_s": float(nnb.sum()) / dt, "threads": 1}
+    finally:
+        oracle.set_num_threads(threads)
+    return out
+
+
+def large_run(R, torch, W):
+    """Wall time of setup + local factorisations + solve on the large
+    configurations: the 4.2M-point lattices at h/sigma 0.6, 0.8 and 1.0 (FP64
+    and mixed to 1e-12) and the 50M-point lattice (mixed to 1e-12, then FP64 to
+    1e-14), each through the device entry points on one stream."""
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def run(w, prec, rtol):
+        pts = w.points()
+        d_pts = torch.tensor(pts, device="cuda")
+        d_f = torch.tensor(w.values(pts), device="cuda")
+        del pts
+        d_lam = torch.empty(w.n, device="cuda", dtype=torch.float64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+        try:
+            R.rbf_precond_setup(h, prec, stream)
+            info, st = R.rbf_solve_device(h, d_lam, R.default_opts(rtol=rtol, precision=prec,
+                                                                  stream=stream),
+                                          ok=(R.RBF_OK, R.RBF_ENOCONV))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            R.rbf_destroy(h)
+        d = info.as_dict()
+        del d_pts, d_f, d_lam
+        return {"n": w.n, "s_to_tol": dt, "rtol": rtol, "status": R.status_name(st),
+                "iterations": d["iterations"], "outer": d["outer_iterations"],
+                "rel_residual": d["rel_residual"], "t_pcsetup": d["t_pcsetup"]}
+
+    for name in ("c2_0.6", "c2_0.8", "c2_1.0"):
+        w = W.WORKLOADS[name]
+        for tag, prec in (("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED)):
+            out[f"{name}_{tag}"] = run(w, prec, 1e-12)
+            log("large", name, tag, out[f"{name}_{tag}"])
+    w = W.WORKLOADS["c4"]
+    for tag, prec, rtol in (("mixed", R.RBF_MIXED, 1e-12), ("fp64", R.RBF_FP64, 1e-14)):
+        out[f"c4_{tag}"] = run(w, prec, rtol)
+        log("large", "c4", tag, out[f"c4_{tag}"])
+    return out
 
 
 def main():
@@ -296,7 +384,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--cpu-side", type=int, default=300, help="oracle sample lattice side")
+    ap.add_argument("--cpu-side", type=int, default=0,
+                    help="oracle lattice side (0: the workload itself)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 4.2M-point and 50M-point legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -480,6 +571,8 @@ def main():
         finally:
             R.rbf_destroy(h)
         werr = float(torch.linalg.norm(d_lam - lam64) / torch.linalg.norm(lam64))
+        lam_mx_host = d_lam.cpu().numpy()
+        lam_64_host = lam64.cpu().numpy()
         h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
         try:
             R.rbf_precond_setup(h, R.RBF_FP64, stream)
@@ -502,6 +595,7 @@ def main():
                  "interp_rel_diff_mixed_vs_fp64": float((s_mx - s_64).abs().max() / s_64.abs().max()),
                  "evaluate_ms": t_ev, "evaluations_per_s": tg.shape[0] / (t_ev * 1e-3)}
         log("mixed", mixed)
+        s_mx_host, s_64_host = s_mx.cpu().numpy(), s_64.cpu().numpy()
 
     # ---- evaluation of the interpolant at separate targets (eq. rbf1; the
     # remeshing use): the staggered lattice between the nodes and seeded
@@ -536,11 +630,34 @@ def main():
                                                            packed=e, n_hi=args.serve_n_hi)
                 log("serving", tag, e, "engines", serving[f"{tag}_engines{e}"])
 
+    large = None
+    if not args.no_large:
+        large = large_run(R, torch, W)
+
     cpu = None
+    oracle_cmp = None
     if not args.no_cpu:
-        log("cpu baseline: oracle on a", args.cpu_side, "lattice")
-        cpu = cpu_baseline(w, args.cpu_side)
+        side = args.cpu_side or w.n_side
+        log("cpu baseline: oracle on a", side, "lattice")
+        tg_host = W.staggered_lattice(w.n_side) if mixed is not None else None
+        cpu, lam_or, s_or = cpu_baseline(w, side, tg_host)
         log("cpu", cpu)
+        cpu["matvec_1thread"] = oracle_matvec_1thread(["c0", w.name])
+        log("cpu 1-thread matvec", cpu["matvec_1thread"])
+        if lam_or is not None and mixed is not None:
+            # the GPU's weights and interpolants against the oracle's: two
+            # solutions that both meet the tolerance differ by up to
+            # kappa(A) (res1 + res2) in the weights; the interpolants agree far
+            # more closely
+            nl = np.linalg.norm(lam_or)
+            smax = np.abs(s_or).max()
+            oracle_cmp = {
+                "weights_rel_diff_fp64": float(np.linalg.norm(lam_64_host - lam_or) / nl),
+                "weights_rel_diff_mixed": float(np.linalg.norm(lam_mx_host - lam_or) / nl),
+                "interp_rel_diff_fp64": float(np.abs(s_64_host - s_or).max() / smax),
+                "interp_rel_diff_mixed": float(np.abs(s_mx_host - s_or).max() / smax),
+                "oracle_rel_residual": cpu["rel_residual"], "points": int(s_or.shape[0])}
+            log("vs oracle", oracle_cmp)
 
     line = {
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
@@ -558,6 +675,8 @@ def main():
                                             "t_vecmdot", "t_other", "matvecs64",
                                             "precond_applies")},
         "mixed": mixed,
+        "vs_oracle": oracle_cmp,
+        "large": large,
         "p99_latency_s": serving["fp64"]["latency_p99_s"] if serving else None,
         "serving": serving,
         "geometry": geometry,

@@ -14,7 +14,13 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rbf_oracle.c")
-LIB = os.path.join(HERE, "librbf_oracle.so")
+# RBF_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; the process must preload the
+# ASan runtime, see SANITIZE_FLAGS' users in tests/)
+SANITIZE = os.environ.get("RBF_ORACLE_SANITIZE") == "1"
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                  "-fno-omit-frame-pointer", "-g"]
+LIB = os.path.join(HERE, "librbf_oracle_san.so" if SANITIZE else "librbf_oracle.so")
 
 STATUS = {0: "ORC_OK", 1: "ORC_EINVAL", 2: "ORC_EDUPLICATE", 3: "ORC_ENOMEM",
           5: "ORC_ENOTPD", 6: "ORC_ENOCONV", 7: "ORC_EBREAKDOWN", 8: "ORC_ENAN",
@@ -31,6 +37,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, OpenMP)."""
     if force or not os.path.exists(LIB):
         cmd = ["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+               *(SANITIZE_FLAGS if SANITIZE else []),
                "-shared", "-o", LIB + ".tmp", SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)
@@ -67,6 +74,8 @@ def lib():
                                 C.c_int]
         L.orc_rel_residual.argtypes = [vp, dp, dp, dp]
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         L.orc_set_geometry.argtypes = [vp, C.c_double, C.c_double, C.c_double]
         L.orc_subdomains.argtypes = [vp, lp]
         _lib = L
@@ -101,6 +110,10 @@ class SolveInfo:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 class Problem:

@@ -92,6 +92,14 @@ int orc_num_threads(void) {
 #endif
 }
 
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---- the kernel phi (Section 2.3) ------------------------------------------ */
 
 static double gauss_norm(double sigma) { return 1.0 / (2.0 * M_PI * sigma * sigma); }

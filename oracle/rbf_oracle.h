@@ -98,8 +98,10 @@ int orc_gmres(orc_problem* p, const double* f, int restart, double rtol, int max
 /* ||f - A x||_2 / ||f||_2 with the truncated matrix. */
 int orc_rel_residual(const orc_problem* p, const double* f, const double* x, double* out);
 
-/* Number of OpenMP threads the oracle runs with. */
+/* Number of OpenMP threads the oracle runs with; set it (n > 0) for the
+ * calls that follow on the calling thread. */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

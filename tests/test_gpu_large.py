@@ -80,6 +80,9 @@ def test_c2_fp64_and_mixed(torch_dev, oracle_mod, name):
         assert np.linalg.norm(f - y) / np.linalg.norm(f) <= 1e-12 * (1 + w.n * 2.0 ** -53)
         err, res = sampled_rows(oracle_mod, pts, w, lam, y, f, 2000, 11 + prec)
         say(name, prec, "sampled matvec error / bar", err, "sampled residual", res)
+        d = info.as_dict()
+        say(name, prec, "iterations", d["iterations"], "outer", d.get("outer_iterations"),
+            "shifted blocks", d.get("shifted_blocks"))
         assert err <= 1e-13, err
         assert res <= 1e-10, res
 
