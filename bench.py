@@ -353,7 +353,7 @@ def large_run(R, torch, W):
         try:
             R.rbf_precond_setup(h, prec, stream)
             info, st = R.rbf_solve_device(h, d_lam, R.default_opts(rtol=rtol, precision=prec,
-                                                                  stream=stream),
+                                                                  stream=stream, max_iters=300),
                                           ok=(R.RBF_OK, R.RBF_ENOCONV))
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0

@@ -47,7 +47,8 @@ typedef enum {
     RBF_ENOMEM = 3,       /* device allocation failed or max_device_bytes exceeded */
     RBF_EDEVICE = 4,      /* a HIP runtime error */
     RBF_ENOTPD = 5,       /* a local block failed its Cholesky factorisation */
-    RBF_ENOCONV = 6,      /* iteration limit reached; best iterate is returned */
+    RBF_ENOCONV = 6,      /* iteration limit reached, or (RBF_MIXED) refinement
+                             stalled; the last accepted iterate is returned */
     RBF_EBREAKDOWN = 7,   /* Arnoldi breakdown with a residual above tolerance */
     RBF_ENAN = 8,         /* a NaN or Inf appeared in an iterate */
     RBF_ESTATE = 9,       /* call out of order (e.g. evaluate before a solve) */
@@ -69,7 +70,9 @@ typedef struct {
                                A the cutoff-truncated matrix (default 1e-10) */
     rbf_precision precision;
     double inner_rtol;      /* RBF_MIXED: inner GMRES relative tolerance (default 1e-4) */
-    int max_outer;          /* RBF_MIXED: outer refinement steps (default 60) */
+    int max_outer;          /* RBF_MIXED: outer refinement steps (default 60); an
+                               outer step that does not lower the FP64 residual is
+                               undone and the solve ends with RBF_ENOCONV */
     size_t max_device_bytes;/* 0 = no limit; else fail with RBF_ENOMEM beyond it */
     void* stream;           /* hipStream_t for every launch of the call */
 } rbf_solve_opts;

@@ -1200,10 +1200,25 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
             }
         }
     } else {
-        // mixed: FP64 residual, FP32 inner GMRES on A d = r, FP64 update
+        // mixed: FP64 residual, FP32 inner GMRES on A d = r, FP64 update.  An
+        // outer step that does not lower the FP64 residual (the FP32 product's
+        // error times a large correction outweighs what the inner solve
+        // removed: kappa(A) u32 near or above 1) is undone, and the refinement
+        // stops there with the previous iterate.
+        double prev = 0.0;
         for (;;) {
             RBF_TRY(true_rel_residual(p, p->fs, p->x, bnorm, &rel, st, &pt));
             p->history.push_back(rel);
+            if (outer > 0 && !(rel < prev)) {
+                HIP_TRY(hipMemcpyAsync(p->x, p->rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+                const double worse = rel;
+                rel = prev;
+                status = fail(RBF_ENOCONV,
+                              "refinement stalled after %d outer steps: residual %.3e, the next "
+                              "step gave %.3e",
+                              outer - 1, rel, worse);
+                break;
+            }
             if (!std::isfinite(rel)) {
                 status = fail(RBF_ENAN, "non-finite residual");
                 break;
@@ -1222,7 +1237,11 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
             RBF_TRY(gmres_cycles(p, RBF_MIXED, p->rhs, p->d, m,
                                  std::max(opts.inner_rtol * rnorm, 0.5 * opts.rtol * bnorm), 1,
                                  opts.max_iters - iters, st, &cr, &pt, p->rhs));
+            // the inner solve is done with its right-hand side: keep the
+            // iterate there in case this step has to be undone
+            HIP_TRY(hipMemcpyAsync(p->rhs, p->x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
             HIP_TRY(rbf::launch_axpy(1.0, p->d, p->x, n, st));
+            prev = rel;
             iters += cr.iters;
             cycles += cr.cycles;
             ++outer;
@@ -1379,6 +1398,8 @@ struct EngProb {
     int j = 0, k = 0;
     std::vector<double> H, cs, sn, gv, yv;
     double bnorm = 0, rel = 0, tol_abs = 0, est = 0;
+    double prev = 0;     // mixed: the residual before the current outer step
+    bool undo = false;   // mixed: the current outer step changed x (its old x is in p->rhs)
     int iters = 0, cycles = 0, outer = 0, mv64 = 0, mv32 = 0, pc = 0;
     bool breakdown = false;
     int slot = -1;   // its result slot, kept while it is active
@@ -1632,9 +1653,11 @@ public:
                 Rj.v = p->w;
                 Rj.z = p->z;
                 VecJob& U = host<VecJob>(L.vec[kVUpd])[i];
-                U.op = VecJob::kAxpy;
+                U.op = q.mixed ? VecJob::kAxpyKeep : VecJob::kAxpy;   // mixed: keep the old x
                 U.a = p->z;
                 U.y = p->x;
+                U.keep = p->rhs;
+                if (q.mixed) q.undo = true;
                 resid();
                 break;
             }
@@ -1648,6 +1671,22 @@ public:
         p->history.push_back(q.rel);
         rbf_status s = RBF_OK;
         std::string msg;
+        if (q.mixed && q.outer > 0 && !(q.rel < q.prev)) {   // as the lone solve: undo, stop
+            if (q.undo &&
+                hipMemcpyAsync(p->x, p->rhs, sizeof(double) * p->n, hipMemcpyDeviceToDevice, st) !=
+                    hipSuccess) {
+                finish(q, done, RBF_EDEVICE, "copy failed");
+                return false;
+            }
+            const double worse = q.rel;
+            q.rel = q.prev;
+            char buf[160];
+            snprintf(buf, sizeof buf,
+                     "refinement stalled after %d outer steps: residual %.3e, the next step gave %.3e",
+                     q.outer - 1, q.rel, worse);
+            finish(q, done, RBF_ENOCONV, buf);
+            return false;
+        }
         if (!std::isfinite(q.rel)) {
             s = RBF_ENAN;
             msg = "non-finite residual";
@@ -1666,9 +1705,11 @@ public:
                 finish(q, done, RBF_ENAN, "non-finite residual");
                 return false;
             }
+            q.prev = q.rel;
             if (beta <= q.tol_abs) {   // nothing to do in this cycle
                 if (q.mixed) {
                     ++q.outer;
+                    q.undo = false;
                     q.st = EngProb::kResid;
                     return true;
                 }

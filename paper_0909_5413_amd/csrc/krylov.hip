@@ -185,6 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_vec_packed(const VecJob* __restrict_
     for (long long i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
         if (op == VecJob::kSub) Y[i] = A[i] - Bv[i];
         else if (op == VecJob::kAxpy) Y[i] = __builtin_fma(1.0, A[i], Y[i]);
+        else if (op == VecJob::kAxpyKeep) {
+            const double yi = Y[i];
+            J.keep[i] = yi;
+            Y[i] = __builtin_fma(1.0, A[i], yi);
+        }
         else if (op == VecJob::kFill) Y[i] = 0.0;
         else if (op == VecJob::kScaleByInv) Y[i] = A[i] / d;
     }

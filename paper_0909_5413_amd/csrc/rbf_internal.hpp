@@ -296,9 +296,11 @@ hipError_t launch_sum_counts(const int* nnb, long long n, long long* partial_out
 int dot_blocks(long long n);   // launch_multidot's grid
 int vec_blocks(long long n);   // the element-wise kernels' grid
 struct VecJob {
-    enum : int { kSub = 0, kAxpy = 1, kFill = 2, kScaleByInv = 3, kMultiAxpy = 4, kNop = 5 };
+    enum : int { kSub = 0, kAxpy = 1, kFill = 2, kScaleByInv = 3, kMultiAxpy = 4, kNop = 5,
+                 kAxpyKeep = 6 };
     int op;                  // y = a - b | y += a | y = 0 | y = a / sqrt(den[0]) |
-                             // y = sign * sum_k coef[k] a[k * ld ..] + (overwrite ? 0 : y) | none
+                             // y = sign * sum_k coef[k] a[k * ld ..] + (overwrite ? 0 : y) | none |
+                             // b = y, then y += a (b written: the old y kept)
     int nv;                  // multi-axpy: vectors (<= 64)
     int overwrite;
     long long n, ld;
@@ -307,6 +309,7 @@ struct VecJob {
     const double* den;
     const double* coef;      // multi-axpy coefficients (device)
     double* y;
+    double* keep;            // kAxpyKeep: where the old y goes
     double sign;
 };
 struct DotJob {              // out[k] = <V_k, w>, k < nv, partials in partial (nv = 0: none)

@@ -373,3 +373,36 @@ def test_resume_from_lambda0(torch_dev, oracle_mod):
     assert i2["t_pcsetup"] < i1["t_pcsetup"] and i3["t_pcsetup"] < i1["t_pcsetup"]
     P = oracle_mod.Problem(pts, w.sigma, w.cutoff, 1)
     assert P.rel_residual(f, lam2) <= residual_gate(P, f, lam2, 1e-12)
+
+
+def test_mixed_refinement_never_returns_a_worse_iterate(torch_dev, oracle_mod):
+    """h/sigma = 0.6 (kappa(A) u32 >> 1): FP32 inner solves cannot reduce the
+    FP64 residual for long.  An outer step that does not lower it is undone
+    and the solve stops with RBF_ENOCONV: the reported residual is the
+    smallest of the history (each accepted step lowered it), it is below the
+    starting one, and the oracle's residual of the returned weights agrees
+    with it, so the returned iterate is the one the residual belongs to."""
+    pts, sigma = lattice(60, 0.6, 31)
+    f = W.gaussian_vortex(pts, 0.2)
+    n = pts.shape[0]
+    say("mixed refinement at h/sigma 0.6", n)
+    h = R.rbf_setup(pts, f, sigma, 6 * sigma, 1)
+    try:
+        lam, info, st = R.rbf_solve(h, n, R.default_opts(rtol=1e-12, precision=R.RBF_MIXED,
+                                                          max_iters=900),
+                                    ok=(R.RBF_ENOCONV,))
+        d = info.as_dict()
+    finally:
+        R.rbf_destroy(h)
+    hist = d["history"]
+    say("outer", d["outer_iterations"], "iterations", d["iterations"], "history", hist)
+    assert st == R.RBF_ENOCONV
+    assert np.all(np.isfinite(lam))
+    assert d["rel_residual"] == min(hist)
+    assert d["rel_residual"] < hist[0]
+    assert all(b < a for a, b in zip(hist[:-2], hist[1:-1]))   # accepted steps
+    P = oracle_mod.Problem(pts, sigma, 6 * sigma, 1)
+    res = P.rel_residual(f, lam)
+    slack = residual_gate(P, f, lam, 0.0)
+    say("oracle residual", res, "reported", d["rel_residual"], "slack", slack)
+    assert abs(res - d["rel_residual"]) <= slack

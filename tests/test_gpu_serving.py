@@ -211,3 +211,36 @@ def test_block_cache_reuse_is_clean(torch_dev):
     assert np.array_equal(lam1, lam0)
     R.rbf_block_cache(-1, trim=True)
     assert R.rbf_block_cache(-1) == 0
+
+
+def test_stalled_mixed_requests_equal_alone(torch_dev):
+    """Mixed requests at h/sigma = 0.6, whose outer refinement stalls and is
+    undone: served by the packed engines (and by one stream per request) each
+    ends as it does alone, with the same status, residual and weights."""
+    reqs = W.serving_requests(3, seed_base=999000, n_lo=2e3, n_hi=8e3, hs_lo=0.6, hs_hi=0.62)
+    data = [(w, w.points()) for w in reqs]
+    opts = dict(rtol=1e-12, precision=R.RBF_MIXED, max_iters=600)
+    ref = []
+    for w, pts in data:
+        f = w.values(pts)
+        h = R.rbf_setup(pts, f, w.sigma, w.cutoff, w.overlap)
+        try:
+            lam, info, st = R.rbf_solve(h, w.n, R.default_opts(**opts),
+                                        ok=(R.RBF_OK, R.RBF_ENOCONV))
+            ref.append((lam, st, info.rel_residual))
+        finally:
+            R.rbf_destroy(h)
+        say("alone", w.name, w.n, R.status_name(st), ref[-1][2])
+    for packed in (2, 0):
+        srv = R.rbf_server_create(max_active=3, packed=packed)
+        try:
+            ids = [R.rbf_server_submit(srv, pts, w.values(pts), w.sigma, w.cutoff, w.overlap,
+                                       R.default_opts(**opts)) for w, pts in data]
+            for (w, _), rid, (lam0, st0, rel0) in zip(data, ids, ref):
+                lam, res, st = R.rbf_server_wait(srv, rid, w.n)
+                say("served", packed, w.name, R.status_name(st), res.info.rel_residual)
+                assert st == st0
+                assert res.info.rel_residual == rel0
+                assert np.array_equal(lam, lam0)
+        finally:
+            R.rbf_server_destroy(srv)
