@@ -106,8 +106,13 @@ __device__ __forceinline__ double exp_neg_t32(double x, const double* T) {
 // shift; f = y - k comes from a second fused multiply-add of the same exact
 // product (one rounding, |f| <= 1/2), so no split constant is needed: the
 // reduction's only error is beta's own rounding.  2^(f/32) = exp(f ln2/32) is
-// the degree-6 Taylor polynomial in f with coefficients (ln2/32)^i / i!
-// (truncation below (ln2/64)^7/7! < 3.5e-18).  Valid for -700*32/ln2 < y <= 0.
+// the degree-5 polynomial interpolating it at the six Chebyshev points of
+// [-1/2, 1/2] (coefficients solved and rounded by gen_constants.py, which
+// checks in exact arithmetic that the rounded polynomial stays within
+// 1.41e-16 relative of exp there): one multiply-add fewer than the degree-6
+// Taylor polynomial, for an exponential within 5.2e-16 relative instead of
+// 4e-16 (table entry and three roundings included).
+// Valid for -700*32/ln2 < y <= 0.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double exp2_scaled_t32(double d2, double beta, const double* T) {
     const double kShift = 0x1.8p52;
@@ -115,12 +120,11 @@ __device__ __forceinline__ double exp2_scaled_t32(double d2, double beta, const 
     const double kf = t - kShift;
     const int k = (int)__double2loint(t);
     const double f = __builtin_fma(d2, beta, -kf);
-    double p = 0x1.430912f86c787p-43;                 // (ln2/32)^6/6!
-    p = __builtin_fma(p, f, 0x1.5d87fe78a6731p-35);    // (ln2/32)^5/5!
-    p = __builtin_fma(p, f, 0x1.3b2ab6fba4e77p-27);    // (ln2/32)^4/4!
-    p = __builtin_fma(p, f, 0x1.c6b08d704a0c0p-20);    // (ln2/32)^3/3!
-    p = __builtin_fma(p, f, 0x1.ebfbdff82c58fp-13);    // (ln2/32)^2/2!
-    p = __builtin_fma(p, f, 0x1.62e42fefa39efp-6);     // (ln2/32)^1/1!
+    double p = 0x1.5d885e6ef14a6p-35;
+    p = __builtin_fma(p, f, 0x1.3b2b301f1eb9cp-27);
+    p = __builtin_fma(p, f, 0x1.c6b08d70380ddp-20);
+    p = __builtin_fma(p, f, 0x1.ebfbdff7feebap-13);
+    p = __builtin_fma(p, f, 0x1.62e42fefa39efp-6);
     p = __builtin_fma(p, f, 1.0);
     return __builtin_amdgcn_ldexp(T[k & 31] * p, k >> 5);
 }

@@ -87,7 +87,7 @@ def test_device_exp_constants_accurate():
         got = _device_exp(float(x))
         ref = math.exp(float(x))
         worst = max(worst, abs(got - ref) / ref)
-    assert worst < 4e-16, worst
+    assert worst < 5.2e-16, worst
 
 
 def _device_exp_t32(x):
@@ -146,8 +146,9 @@ def _device_exp2_scaled(d2, beta):
     body = body[:body.index("return __builtin_amdgcn_ldexp")]
     shift = float.fromhex(re.search(r"const double kShift = ([0-9a-fx.p+-]+);", body).group(1))
     first = float.fromhex(re.search(r"double p = ([0-9a-fx.p+-]+);", body).group(1))
-    coefs = [float.fromhex(h) for h in re.findall(r"(0x[0-9a-f.]+p[+-]?\d+)\);\s*// \(ln2", body)]
-    assert len(coefs) == 5
+    coefs = [float.fromhex(h) for h in
+             re.findall(r"__builtin_fma\(p, f, (0x[0-9a-f.]+p[+-]?\d+)\)", body)]
+    assert len(coefs) == 4 and re.search(r"__builtin_fma\(p, f, 1\.0\)", body)
     t = _fma(d2, beta, shift)
     kf = t - shift
     k = int(kf)
@@ -162,9 +163,14 @@ def _device_exp2_scaled(d2, beta):
 
 def test_device_exp2_scaled_constants_accurate():
     """The list matvec's exponential, 2^(d2 beta / 32) with the reduction read
-    from two fused products: within a few units of the last place of the exact
-    2^(d2 beta / 32) (beta taken as exact), over the cutoff's range and beyond,
-    including the tie points y = k + 1/2."""
+    from two fused products and a degree-5 polynomial: within a few units of
+    the last place of the exact 2^(d2 beta / 32) (beta taken as exact), over
+    the cutoff's range and beyond, including the tie points y = k + 1/2, where
+    the reduced argument reaches the ends of the polynomial's interval.  The
+    bar adds the polynomial's own error (1.41e-16, checked in rationals by
+    gen_constants.py), u = 2^-53 for each of the last Horner step, the table
+    entry and the final product, and a little for the earlier Horner steps:
+    5.2e-16."""
     from decimal import Decimal, getcontext
     getcontext().prec = 50
     rng = np.random.default_rng(5)
@@ -180,4 +186,4 @@ def test_device_exp2_scaled_constants_accurate():
         y = y * Decimal(Fraction(beta).numerator) / Decimal(Fraction(beta).denominator)
         ref = float(Decimal(2) ** (y / 32))
         worst = max(worst, abs(got - ref) / ref)
-    assert worst < 4e-16, worst
+    assert worst < 5.2e-16, worst
