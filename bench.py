@@ -187,6 +187,15 @@ def eval_run(R, torch, w, d_pts, d_f, d_lam, stream, opts):
     try:
         R.rbf_precond_setup(h, R.RBF_FP64, stream)
         R.rbf_solve_device(h, d_lam, opts)
+        # candidates: the sources of the 3x3 cell block around each target's
+        # (clamped) cell, every one of which the kernel evaluates
+        (x0, y0, _, inv), (ncx, ncy) = R.rbf_grid(h)
+        _, _, cs = R.rbf_binning(h, w.n)
+        cnt = np.diff(cs.astype(np.int64)).reshape(ncy, ncx)
+        pad = np.zeros((ncy + 2, ncx + 2), np.int64)
+        pad[1:-1, 1:-1] = cnt
+        block = sum(pad[1 + dy:ncy + 1 + dy, 1 + dx:ncx + 1 + dx]
+                    for dy in (-1, 0, 1) for dx in (-1, 0, 1))
         for name, tg in sets.items():
             d_t = torch.tensor(tg, device=d_pts.device)
             m = tg.shape[0]
@@ -197,9 +206,14 @@ def eval_run(R, torch, w, d_pts, d_f, d_lam, stream, opts):
             ms = event_median(torch, stream, lambda: R.rbf_evaluate_device(h, d_t, m, d_s, stream),
                               3, 20)
             rate = inter / (ms * 1e-3)
+            cx = np.clip(np.floor((tg[:, 0] - x0) * inv).astype(np.int64), 0, ncx - 1)
+            cy = np.clip(np.floor((tg[:, 1] - y0) * inv).astype(np.int64), 0, ncy - 1)
+            cand = int(block[cy, cx].sum())
             out[name] = {"targets": m, "ms": ms, "evaluations_per_s": m / (ms * 1e-3),
                          "interactions": inter, "interactions_per_s": rate,
-                         "frac_r64": rate * OPS_PER_INTERACTION / VALU_OPS_PER_S}
+                         "frac_r64": rate * OPS_PER_INTERACTION / VALU_OPS_PER_S,
+                         "candidate_pairs": cand, "in_cutoff_share": inter / cand,
+                         "candidate_pairs_per_s": cand / (ms * 1e-3)}
     finally:
         R.rbf_destroy(h)
     return out
