@@ -610,6 +610,30 @@ def main():
                  "evaluate_ms": t_ev, "evaluations_per_s": tg.shape[0] / (t_ev * 1e-3)}
         log("mixed", mixed)
         s_mx_host, s_64_host = s_mx.cpu().numpy(), s_64.cpu().numpy()
+        # the FP64 method with the FP32 local inverses as its preconditioner
+        popts = R.default_opts(rtol=w.rtol, precision=R.RBF_FP64_PC32, stream=stream)
+        pc32_t = []
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
+            try:
+                R.rbf_precond_setup(h, R.RBF_FP64_PC32, stream)
+                pinfo, pst = R.rbf_solve_device(h, d_lam, popts, ok=(R.RBF_OK, R.RBF_ENOCONV))
+                torch.cuda.synchronize()
+                pc32_t.append(time.perf_counter() - t1)
+                pinfo = pinfo.as_dict()
+            finally:
+                R.rbf_destroy(h)
+        lam_pc_host = d_lam.cpu().numpy()
+        mixed["fp64_pc32"] = {
+            "s_to_tol": float(np.median(pc32_t)), "status": R.status_name(pst),
+            "iterations": pinfo["iterations"], "rel_residual": pinfo["rel_residual"],
+            "t_pcsetup": pinfo["t_pcsetup"], "t_matsolve": pinfo["t_matsolve"],
+            "shifted_blocks": pinfo["shifted_blocks"],
+            "weight_rel_diff_vs_fp64": float(np.linalg.norm(lam_pc_host - lam_64_host)
+                                             / np.linalg.norm(lam_64_host))}
+        log("fp64 with fp32 local inverses", mixed["fp64_pc32"])
 
     # ---- evaluation of the interpolant at separate targets (eq. rbf1; the
     # remeshing use): the staggered lattice between the nodes and seeded
@@ -668,6 +692,7 @@ def main():
             oracle_cmp = {
                 "weights_rel_diff_fp64": float(np.linalg.norm(lam_64_host - lam_or) / nl),
                 "weights_rel_diff_mixed": float(np.linalg.norm(lam_mx_host - lam_or) / nl),
+                "weights_rel_diff_fp64_pc32": float(np.linalg.norm(lam_pc_host - lam_or) / nl),
                 "interp_rel_diff_fp64": float(np.abs(s_64_host - s_or).max() / smax),
                 "interp_rel_diff_mixed": float(np.abs(s_mx_host - s_or).max() / smax),
                 "oracle_rel_residual": cpu["rel_residual"], "points": int(s_or.shape[0])}

@@ -57,7 +57,14 @@ typedef enum {
                              block larger than RBF_MAX_BLOCK) */
 } rbf_status;
 
-typedef enum { RBF_FP64 = 0, RBF_MIXED = 1 } rbf_precision;
+/* RBF_FP64: every step in FP64.  RBF_MIXED: FP32 matvec and FP32 local
+ * factors inside inner GMRES solves, FP64 outer residual, Arnoldi and update
+ * (iterative refinement).  RBF_FP64_PC32: the FP64 method (FP64 matvec,
+ * Arnoldi, residual and update) right-preconditioned with the FP32 local
+ * factors' centre rows, applied to the FP64 vector with FP64 sums: a fixed
+ * linear preconditioner, so the solve and its stopping test are the FP64
+ * method's, with half the preconditioner's bytes. */
+typedef enum { RBF_FP64 = 0, RBF_MIXED = 1, RBF_FP64_PC32 = 2 } rbf_precision;
 typedef enum { RBF_ORDER_ORIGINAL = 0, RBF_ORDER_SORTED = 1 } rbf_order;
 
 #define RBF_MAX_BLOCK 1536          /* largest overlapping-subdomain size */
@@ -95,7 +102,7 @@ typedef struct {
     size_t device_bytes;    /* bytes the handle holds on the device */
     int history_len;        /* entries in history (valid until the next call) */
     const double* history;  /* true relative residual at each cycle start and end */
-    int shifted_blocks;     /* RBF_MIXED: local blocks factored with a diagonal
+    int shifted_blocks;     /* RBF_MIXED, RBF_FP64_PC32: local blocks factored with a diagonal
                                shift (FP32 Cholesky breakdown), else 0 */
 } rbf_solve_info;
 
@@ -143,7 +150,8 @@ rbf_status rbf_set_geometry(rbf_problem* p, const rbf_geometry* geo, void* strea
 
 /* Factor every local block (Section 2.2: A_i on the overlapping subdomain,
  * untruncated Gaussian, dense Cholesky) and keep the centre rows of its inverse.
- * precision RBF_MIXED stores them in FP32.  rbf_solve calls this when needed;
+ * precisions RBF_MIXED and RBF_FP64_PC32 store them in FP32 (one FP32 set serves
+ * both).  rbf_solve calls this when needed;
  * calling it first separates its time.  Errors: RBF_ENOTPD, RBF_ENOMEM. */
 rbf_status rbf_precond_setup(rbf_problem* p, rbf_precision precision, void* stream);
 
@@ -215,7 +223,8 @@ rbf_status rbf_binning(const rbf_problem* p, int* cell_of, int* perm, int* cell_
 rbf_status rbf_neighbor_counts(rbf_problem* p, int* nnb, long long* total);
 
 /* y = A w (Section 2.3, truncated normalised Gaussian) on device vectors in the
- * given order; precision RBF_MIXED runs the FP32 kernel (FP64 in and out). */
+ * given order; precision RBF_MIXED runs the FP32 kernel (FP64 in and out);
+ * RBF_FP64_PC32 is not a matvec precision (RBF_EINVAL). */
 rbf_status rbf_matvec_device(rbf_problem* p, const double* d_w, double* d_y,
                              rbf_precision precision, rbf_order order, void* stream);
 
@@ -237,7 +246,9 @@ rbf_status rbf_matvec_device_noalloc(rbf_problem* p, const double* d_w, double* 
                                      rbf_precision precision, void* stream);
 
 /* z = M^{-1} v, RASM (Section 2.2, eq. rasm), on device vectors; builds the
- * preconditioner of that precision first if needed. */
+ * preconditioner of that precision first if needed.  RBF_MIXED applies the
+ * FP32 centre rows in FP32 (v rounded to FP32, Kahan sums); RBF_FP64_PC32
+ * applies the same FP32 centre rows to the FP64 v with FP64 sums. */
 rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d_z,
                                     rbf_precision precision, rbf_order order,
                                     void* stream);

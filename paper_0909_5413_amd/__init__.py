@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "librbf_hip.so")
 
 RBF_OK, RBF_EINVAL, RBF_EDUPLICATE, RBF_ENOMEM, RBF_EDEVICE = 0, 1, 2, 3, 4
 RBF_ENOTPD, RBF_ENOCONV, RBF_EBREAKDOWN, RBF_ENAN, RBF_ESTATE, RBF_ELIMIT = 5, 6, 7, 8, 9, 10
-RBF_FP64, RBF_MIXED = 0, 1
+RBF_FP64, RBF_MIXED, RBF_FP64_PC32 = 0, 1, 2
 RBF_ORDER_ORIGINAL, RBF_ORDER_SORTED = 0, 1
 RBF_MAX_BLOCK = 1536
 RBF_MAX_CELL_POINTS = 1536

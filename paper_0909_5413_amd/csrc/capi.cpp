@@ -853,14 +853,22 @@ rbf_status precond_setup_impl(rbf_problem* p, hipStream_t st) {
     return RBF_OK;
 }
 
+// the FP32 local factors serve both the mixed form and the FP64 method with
+// FP32 local inverses
 rbf_status precond_setup(rbf_problem* p, rbf_precision prec, hipStream_t st) {
     if (prec == RBF_FP64) return precond_setup_impl<double>(p, st);
-    if (prec == RBF_MIXED) return precond_setup_impl<float>(p, st);
+    if (prec == RBF_MIXED || prec == RBF_FP64_PC32) return precond_setup_impl<float>(p, st);
     return fail(RBF_EINVAL, "unknown precision %d", (int)prec);
+}
+
+// the matvec's precision under a solve's precision: FP32 only in the mixed form
+inline rbf_precision operator_precision(rbf_precision prec) {
+    return prec == RBF_MIXED ? RBF_MIXED : RBF_FP64;
 }
 
 rbf_status matvec(rbf_problem* p, rbf_precision prec, const double* w, double* y, hipStream_t st) {
     const bool lists = p->nl.nunits > 0;
+    prec = operator_precision(prec);
     if (prec == RBF_FP64) {
         if (lists)
             HIP_TRY(rbf::launch_matvec64_lists(p->mv_args(), p->nl, w, y, st));
@@ -879,8 +887,10 @@ rbf_status rasm(rbf_problem* p, rbf_precision prec, const double* v, double* z, 
     RBF_TRY(precond_setup(p, prec, st));
     if (prec == RBF_FP64) {
         HIP_TRY(rbf::launch_rasm_apply64(p->pc_args(), p->Z64, v, z, st));
-    } else {
+    } else if (prec == RBF_MIXED) {
         HIP_TRY(rbf::launch_rasm_apply32(p->pc_args(), p->Z32, v, z, st));
+    } else {
+        HIP_TRY(rbf::launch_rasm_apply32x64(p->pc_args(), p->Z32, v, z, st));
     }
     return RBF_OK;
 }
@@ -1022,7 +1032,7 @@ rbf_status gmres_cycles(rbf_problem* p, rbf_precision prec, const double* b, dou
             HIP_TRY(hipEventRecord(p->pev[1], st));
             timed = true;
             HIP_TRY(rbf::launch_sub(b, p->w, V, n, st));
-            (prec == RBF_FP64 ? pt->mv64 : pt->mv32) += 1;
+            (operator_precision(prec) == RBF_FP64 ? pt->mv64 : pt->mv32) += 1;
         }
         double beta2;
         RBF_TRY(norm2(p, V, &beta2, st));   // waits for the stream
@@ -1047,7 +1057,7 @@ rbf_status gmres_cycles(rbf_problem* p, rbf_precision prec, const double* b, dou
             pt->pc += 1;
             RBF_TRY(matvec(p, prec, p->z, p->w, st));
             HIP_TRY(hipEventRecord(p->pev[2], st));
-            (prec == RBF_FP64 ? pt->mv64 : pt->mv32) += 1;
+            (operator_precision(prec) == RBF_FP64 ? pt->mv64 : pt->mv32) += 1;
             RBF_TRY(gram_schmidt(p, j, st));
             HIP_TRY(hipEventRecord(p->pev[3], st));
             HIP_TRY(hipEventSynchronize(p->pev[3]));
@@ -1131,7 +1141,8 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
     if (opts.restart < 1 || opts.restart > 63) return fail(RBF_EINVAL, "restart must be in [1, 63]");
     if (!(opts.rtol >= 0)) return fail(RBF_EINVAL, "rtol must be >= 0");
     if (opts.max_iters < 0) return fail(RBF_EINVAL, "max_iters must be >= 0");
-    if (opts.precision != RBF_FP64 && opts.precision != RBF_MIXED)
+    if (opts.precision != RBF_FP64 && opts.precision != RBF_MIXED &&
+        opts.precision != RBF_FP64_PC32)
         return fail(RBF_EINVAL, "unknown precision");
     if (!p->have_values) return fail(RBF_ESTATE, "no right-hand side: pass values or call rbf_set_values");
     p->budget = opts.max_device_bytes;
@@ -1172,7 +1183,7 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
     if (bnorm == 0.0) {
         HIP_TRY(rbf::launch_fill(p->x, 0.0, n, st));
         rel = 0;
-    } else if (opts.precision == RBF_FP64) {
+    } else if (opts.precision != RBF_MIXED) {   // FP64, with FP64 or FP32 local inverses
         for (;;) {
             RBF_TRY(true_rel_residual(p, p->fs, p->x, bnorm, &rel, st, &pt));
             p->history.push_back(rel);
@@ -1187,7 +1198,7 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
                 break;
             }
             CycleResult cr;
-            RBF_TRY(gmres_cycles(p, RBF_FP64, p->fs, p->x, m, opts.rtol * bnorm, 1,
+            RBF_TRY(gmres_cycles(p, opts.precision, p->fs, p->x, m, opts.rtol * bnorm, 1,
                                  opts.max_iters - iters, st, &cr, &pt, p->r));
             iters += cr.iters;
             cycles += cr.cycles;
@@ -1272,7 +1283,7 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
         info->device_bytes = p->bytes;
         info->history_len = (int)p->history.size();
         info->history = p->history.data();
-        info->shifted_blocks = opts.precision == RBF_MIXED ? p->shifted_blocks32 : 0;
+        info->shifted_blocks = opts.precision != RBF_FP64 ? p->shifted_blocks32 : 0;
     }
     return status;
 }
@@ -1540,7 +1551,8 @@ public:
         rbf_problem* p = q.p;
         const long long n = p->n;
         const int prec = (q.mixed && q.st == EngProb::kArnoldi) ? 1 : 0;   // the operator's precision
-        const int rprec = q.mixed ? 1 : 0;                                 // the preconditioner's
+        // the preconditioner's: FP64 Z; FP32 Z with FP32 sums; FP32 Z with FP64 sums
+        const int rprec = q.mixed ? 1 : (q.o.precision == RBF_FP64_PC32 ? 2 : 0);
         for (int v = 0; v < kVPhases; ++v) {
             VecJob& J = host<VecJob>(L.vec[v])[i];
             J = VecJob{};
@@ -1757,13 +1769,13 @@ public:
         info.restarts = q.cycles;
         info.rel_residual = q.rel;
         info.t_init = p->t_init;
-        info.t_pcsetup = q.mixed ? p->t_pcsetup32 : p->t_pcsetup64;
+        info.t_pcsetup = q.o.precision == RBF_FP64 ? p->t_pcsetup64 : p->t_pcsetup32;
         info.interactions_per_matvec = p->interactions;
         info.matvecs64 = q.mv64;
         info.matvecs32 = q.mv32;
         info.precond_applies = q.pc;
         info.device_bytes = p->bytes;
-        info.shifted_blocks = q.mixed ? p->shifted_blocks32 : 0;
+        info.shifted_blocks = q.o.precision == RBF_FP64 ? 0 : p->shifted_blocks32;
         p->mark(st);
         done->push_back(EngineDone{q.tag, s, e != hipSuccess ? hipGetErrorString(e) : msg});
         free_slots.push_back(q.slot);
@@ -1944,8 +1956,11 @@ rbf_status engine_add(Engine* e, rbf_problem* p, const rbf_solve_opts& o, double
     if (p->nl.nunits == 0) return fail(RBF_ELIMIT, "the problem has no neighbour lists");
     if (o.restart < 1 || o.restart > 63) return fail(RBF_EINVAL, "restart must be in [1, 63]");
     if (!p->have_values) return fail(RBF_ESTATE, "no right-hand side");
+    if (o.precision != RBF_FP64 && o.precision != RBF_MIXED && o.precision != RBF_FP64_PC32)
+        return fail(RBF_EINVAL, "unknown precision");
     const bool mixed = o.precision == RBF_MIXED;
-    if (mixed ? !p->Z32 : !p->Z64) return fail(RBF_ESTATE, "the preconditioner is not built");
+    if (o.precision == RBF_FP64 ? !p->Z64 : !p->Z32)
+        return fail(RBF_ESTATE, "the preconditioner is not built");
     RBF_TRY(ensure_workspace(p, o.restart, e->st));
     EngProb q;
     q.p = p;
@@ -2243,7 +2258,8 @@ rbf_status rbf_matvec_device_noalloc(rbf_problem* p, const double* d_w, double* 
 rbf_status rbf_precond_apply_device(rbf_problem* p, const double* d_v, double* d_z,
                                     rbf_precision precision, rbf_order order, void* stream) {
     if (!p || !d_v || !d_z) return fail(RBF_EINVAL, "NULL argument");
-    if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_EINVAL, "bad precision");
+    if (precision != RBF_FP64 && precision != RBF_MIXED && precision != RBF_FP64_PC32)
+        return fail(RBF_EINVAL, "bad precision");
     hipStream_t st = as_stream(stream);
     MarkOnExit mk{p, st};
     try {
@@ -2413,9 +2429,9 @@ rbf_status rbf_set_profiling(rbf_problem* p, int enable) {
 rbf_status rbf_setup_kernel_times(const rbf_problem* p, rbf_precision precision, double* ms,
                                   int* launches) {
     if (!p || !ms || !launches) return fail(RBF_EINVAL, "NULL argument");
-    if (precision != RBF_FP64 && precision != RBF_MIXED)
+    if (precision != RBF_FP64 && precision != RBF_MIXED && precision != RBF_FP64_PC32)
         return fail(RBF_EINVAL, "unknown precision %d", (int)precision);
-    const int pi = precision == RBF_FP64 ? 0 : 1;
+    const int pi = precision == RBF_FP64 ? 0 : 1;   // the FP64 or the FP32 local factors
     if (!p->ktimes_valid[pi]) return fail(RBF_ESTATE, "no profiled setup of this precision");
     for (int k = 0; k < RBF_K_SETUP_KINDS; ++k) {
         ms[k] = p->kms[pi][k];

@@ -1290,17 +1290,21 @@ namespace {
 // z[c's points] = Z_c v[members of c], one workgroup per cell: the member
 // values of v gathered into LDS, then Z_c streamed once from HBM.  Each wave
 // takes four rows at a time, a 16-lane group per row (so one load instruction
-// reads four 128-byte row segments), four independent loads per lane in
-// flight, and one 16-lane reduction per row.  FP32 rows accumulate with Kahan
-// compensation.
-template <typename T>
-__device__ __forceinline__ double row_dot(const T* __restrict__ zr, const T* vs, int n_omega,
+// reads four row segments), four independent loads per lane in flight, and one
+// 16-lane reduction per row.  TZ is Z's storage, TV the precision of v and of
+// the sums: FP64 Z with FP64 sums (the FP64 method), FP32 Z with FP32 sums and
+// Kahan compensation (the mixed form's inner solves), and FP32 Z widened into
+// FP64 sums of the FP64 v (the FP64 method with FP32-stored local inverses: a
+// fixed linear operator, so right-preconditioned GMRES is unchanged by it).
+template <typename TZ, typename TV>
+__device__ __forceinline__ double row_dot(const TZ* __restrict__ zr, const TV* vs, int n_omega,
                                           int ph) {
-    if (sizeof(T) == 8) {
+    if (sizeof(TV) == 8) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int q = ph;
         for (; q + 48 < n_omega; q += 64) {
-            const double z0 = zr[q], z1 = zr[q + 16], z2 = zr[q + 32], z3 = zr[q + 48];
+            const double z0 = (double)zr[q], z1 = (double)zr[q + 16], z2 = (double)zr[q + 32],
+                         z3 = (double)zr[q + 48];
             a0 = __builtin_fma(z0, (double)vs[q], a0);
             a1 = __builtin_fma(z1, (double)vs[q + 16], a1);
             a2 = __builtin_fma(z2, (double)vs[q + 32], a2);
@@ -1327,11 +1331,11 @@ struct RasmLds {
     int nr_s, n_omega_s, n_c_s;
 };
 
-template <typename T>
-__device__ __forceinline__ void rasm_cell(PrecondArgs a, const T* __restrict__ Z,
+template <typename TZ, typename TV>
+__device__ __forceinline__ void rasm_cell(PrecondArgs a, const TZ* __restrict__ Z,
                                           const double* __restrict__ v, double* __restrict__ z,
                                           long long c, RasmLds& L) {
-    T* vs = reinterpret_cast<T*>(L.vs);
+    TV* vs = reinterpret_cast<TV*>(L.vs);
     int* rb = L.rb;
     int* re = L.re;
     int& nr_s = L.nr_s;
@@ -1352,28 +1356,28 @@ __device__ __forceinline__ void rasm_cell(PrecondArgs a, const T* __restrict__ Z
     if (n_c == 0) return;
     const int* mlist = a.mem ? a.mem + a.moff[c] : nullptr;
     for (int k = tid; k < n_omega; k += kThreads)
-        vs[k] = (T)v[mlist ? mlist[k] : member_index(rb, re, nr, k)];
+        vs[k] = (TV)v[mlist ? mlist[k] : member_index(rb, re, nr, k)];
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     const int grp = lane >> 4, ph = lane & 15;
-    const T* Zc = Z + a.zoff[c];
+    const TZ* Zc = Z + a.zoff[c];
     const int own = mlist ? 0 : a.cell_start[c];
     for (int r0 = 4 * wave; r0 < n_c; r0 += 4 * (kThreads / 64)) {
         const int r = r0 + grp;
         double sum = 0.0;
-        if (r < n_c) sum = row_dot<T>(Zc + (size_t)r * n_omega, vs, n_omega, ph);
+        if (r < n_c) sum = row_dot<TZ, TV>(Zc + (size_t)r * n_omega, vs, n_omega, ph);
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, RBF_WAVE);
         if (ph == 0 && r < n_c) z[mlist ? mlist[n_omega - n_c + r] : own + r] = sum;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const T* __restrict__ Z,
+template <typename TZ, typename TV>
+__global__ __launch_bounds__(kThreads) void k_rasm_apply(PrecondArgs a, const TZ* __restrict__ Z,
                                                          const double* __restrict__ v,
                                                          double* __restrict__ z) {
     __shared__ RasmLds L;
-    rasm_cell<T>(a, Z, v, z, blockIdx.x, L);
+    rasm_cell<TZ, TV>(a, Z, v, z, blockIdx.x, L);
 }
 
 // Packed form: workgroup b serves subdomain b - block0[j] of job j.
@@ -1392,9 +1396,11 @@ __global__ __launch_bounds__(kThreads) void k_rasm_packed(const RasmJob* __restr
     const long long c = (long long)blockIdx.x - block0[j];
     if (J.skip) return;
     if (J.prec == 0)
-        rasm_cell<double>(J.a, static_cast<const double*>(J.Z), J.v, J.z, c, L);
+        rasm_cell<double, double>(J.a, static_cast<const double*>(J.Z), J.v, J.z, c, L);
+    else if (J.prec == 1)
+        rasm_cell<float, float>(J.a, static_cast<const float*>(J.Z), J.v, J.z, c, L);
     else
-        rasm_cell<float>(J.a, static_cast<const float*>(J.Z), J.v, J.z, c, L);
+        rasm_cell<float, double>(J.a, static_cast<const float*>(J.Z), J.v, J.z, c, L);
 }
 
 // Members of box b (one wave per box): the candidate cells are those of the
@@ -1485,13 +1491,19 @@ hipError_t launch_rasm_packed(const RasmJob* jobs, const int* block0, int njobs,
 
 hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const double* v, double* z,
                                hipStream_t st) {
-    k_rasm_apply<double><<<(unsigned)a.ncells, kThreads, 0, st>>>(a, Z, v, z);
+    k_rasm_apply<double, double><<<(unsigned)a.ncells, kThreads, 0, st>>>(a, Z, v, z);
     return hipGetLastError();
 }
 
 hipError_t launch_rasm_apply32(const PrecondArgs& a, const float* Z, const double* v, double* z,
                                hipStream_t st) {
-    k_rasm_apply<float><<<(unsigned)a.ncells, kThreads, 0, st>>>(a, Z, v, z);
+    k_rasm_apply<float, float><<<(unsigned)a.ncells, kThreads, 0, st>>>(a, Z, v, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_rasm_apply32x64(const PrecondArgs& a, const float* Z, const double* v, double* z,
+                                  hipStream_t st) {
+    k_rasm_apply<float, double><<<(unsigned)a.ncells, kThreads, 0, st>>>(a, Z, v, z);
     return hipGetLastError();
 }
 

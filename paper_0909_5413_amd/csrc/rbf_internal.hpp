@@ -220,6 +220,10 @@ hipError_t launch_rasm_apply64(const PrecondArgs& a, const double* Z, const doub
                                double* z, hipStream_t st);
 hipError_t launch_rasm_apply32(const PrecondArgs& a, const float* Z, const double* v,
                                double* z, hipStream_t st);
+// FP32-stored Z applied to FP64 v with FP64 sums (the FP64 method with FP32
+// local inverses)
+hipError_t launch_rasm_apply32x64(const PrecondArgs& a, const float* Z, const double* v,
+                                  double* z, hipStream_t st);
 
 // Batches of a handle's local factorisations in flight together (1 or 2; 2 by
 // default).  The serving loop keeps its requests to one: they already overlap
@@ -339,7 +343,7 @@ struct MatvecJob {           // y = A w by the lists (prec 0: FP64, 1: FP32)
 // workgroups: nl.ngroups per job; threads: 64 * the largest nl.gunits
 hipError_t launch_matvec_lists_packed(const MatvecJob* jobs, const int* block0, int njobs,
                                       int nblocks, int threads, hipStream_t st);
-struct RasmJob {             // z = M^-1 v (prec 0: FP64 Z, 1: FP32 Z)
+struct RasmJob {             // z = M^-1 v (prec 0: FP64 Z; 1: FP32 Z, FP32 sums; 2: FP32 Z, FP64 sums)
     PrecondArgs a;
     const void* Z;
     const double* v;

@@ -297,6 +297,56 @@ def test_solve_fp64(problems, name, rtol):
     assert np.all(np.abs(R.rbf_evaluate(h, stag) - so) <= 1e-13 * (np.abs(so).max() + 1))
 
 
+@pytest.mark.parametrize("name", ["ragged", "mini"])
+def test_rasm_apply_fp32_rows_fp64_sums(torch_dev, problems, name):
+    """RBF_FP64_PC32's apply: the FP32 centre rows (as rbf_precond_block
+    returns them, widened exactly to FP64) times the FP64 member values, summed
+    in FP64: element by element against the same product formed on the host,
+    within the rounding of two n_omega-term FP64 sums."""
+    say("rasm fp32 rows, fp64 sums", name)
+    h, P, pts, *_ = problems[name]
+    v = W.random_weights(pts.shape[0], 23)
+    dv = torch_dev.tensor(v, device="cuda", dtype=torch_dev.float64)
+    dz = torch_dev.empty_like(dv)
+    R.rbf_precond_apply_device(h, dv, dz, R.RBF_FP64_PC32, R.RBF_ORDER_ORIGINAL,
+                               torch_dev.cuda.current_stream())
+    torch_dev.cuda.synchronize()
+    z = dz.cpu().numpy()
+    u = np.finfo(float).eps / 2
+    ncells = R.rbf_grid(h)[1][0] * R.rbf_grid(h)[1][1]
+    worst = 0.0
+    for cell in range(ncells):
+        mem, Z = R.rbf_precond_block(h, cell, R.RBF_FP64_PC32)
+        if Z.shape[0] == 0:
+            continue
+        own = mem[len(mem) - Z.shape[0]:]
+        assert np.array_equal(Z, Z.astype(np.float32).astype(np.float64))
+        ref = Z @ v[mem]
+        bar = 2 * len(mem) * u * (np.abs(Z) @ np.abs(v[mem])) + 1e-300
+        err = np.abs(z[own] - ref)
+        worst = max(worst, float((err / bar).max()))
+        assert np.all(err <= bar), (cell, float((err / bar).max()))
+    say("worst error / bar", worst)
+
+
+@pytest.mark.parametrize("name,rtol", [("mini", 1e-12), ("c0", 1e-10), ("ragged", 1e-12)])
+def test_solve_fp64_with_fp32_local_inverses(problems, name, rtol):
+    """RBF_FP64_PC32: the FP64 method with the FP32 local inverses as its
+    (fixed, linear) preconditioner reaches the same FP64 residual bar as the
+    FP64 method, judged by the oracle, in about as many iterations."""
+    say("solve fp64 pc32", name)
+    h, P, pts, f, *_ = problems[name]
+    lam, info, st = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=rtol, precision=R.RBF_FP64_PC32))
+    d = info.as_dict()
+    assert d["rel_residual"] <= rtol and d["outer_iterations"] == 0
+    assert d["matvecs32"] == 0 and d["matvecs64"] > 0
+    res = P.rel_residual(f, lam)
+    assert res <= residual_gate(P, f, lam, rtol), (res, d)
+    _, i64, _ = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=rtol))
+    say("iterations pc32", d["iterations"], "fp64", i64.iterations)
+    assert abs(d["iterations"] - i64.iterations) <= max(2, i64.iterations // 5)
+
+
 @pytest.mark.parametrize("name", ["mini", "c0"])
 def test_solve_mixed(problems, name):
     say("solve_mixed", name)

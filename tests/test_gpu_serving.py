@@ -41,7 +41,7 @@ def mix(k, seed_base):
     out = []
     for i, w in enumerate(reqs):
         pts = w.points()
-        out.append((w, pts, w.values(pts), R.RBF_FP64 if i % 2 == 0 else R.RBF_MIXED))
+        out.append((w, pts, w.values(pts), (R.RBF_FP64, R.RBF_MIXED, R.RBF_FP64_PC32)[i % 3]))
     return out
 
 
@@ -154,13 +154,14 @@ def test_admission_budget_and_failures(torch_dev):
 def test_packed_stream_of_uneven_requests(torch_dev):
     """A longer stream through the packed engine: 24 requests of uneven size
     and spacing (h/sigma down to 0.6, so some stop at the iteration cap),
-    FP64 and mixed, at most 6 on the device, arriving while others run: every
+    FP64, mixed and FP64 with FP32 local inverses, at most 6 on the device,
+    arriving while others run: every
     status, iteration count and weight vector equals the lone solve's."""
     reqs = W.serving_requests(24, seed_base=555000, n_lo=1.5e3, n_hi=4e4)
     data = []
     for i, w in enumerate(reqs):
         pts = w.points()
-        data.append((w, pts, w.values(pts), R.RBF_FP64 if i % 3 else R.RBF_MIXED))
+        data.append((w, pts, w.values(pts), (R.RBF_MIXED, R.RBF_FP64, R.RBF_FP64_PC32)[i % 3]))
     srv = R.rbf_server_create(max_active=6)
     try:
         ids = []
