@@ -128,7 +128,8 @@ def serving_run(R, W, k, precision, max_active, max_iters, packed=2, n_hi=1e6):
     status = [st for _, _, st in opened]
     conv = np.array([r.latency for _, r, st in opened if st == R.RBF_OK])
     return {
-        "requests": k, "precision": "fp64" if precision == R.RBF_FP64 else "mixed",
+        "requests": k,
+        "precision": {R.RBF_FP64: "fp64", R.RBF_MIXED: "mixed"}.get(precision, "fp64_pc32"),
         "mode": f"{packed} packed engines" if packed else "one stream per request",
         "max_active": max_active, "max_iters": max_iters, "n_hi": n_hi,
         "converged_latency_p50_s": float(np.percentile(conv, 50)) if conv.size else None,
@@ -381,11 +382,15 @@ def large_run(R, torch, W):
 
     for name in ("c2_0.6", "c2_0.8", "c2_1.0"):
         w = W.WORKLOADS[name]
-        for tag, prec in (("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED)):
+        tags = [("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED)]
+        if name == "c2_0.8":
+            tags.append(("fp64_pc32", R.RBF_FP64_PC32))
+        for tag, prec in tags:
             out[f"{name}_{tag}"] = run(w, prec, 1e-12)
             log("large", name, tag, out[f"{name}_{tag}"])
     w = W.WORKLOADS["c4"]
-    for tag, prec, rtol in (("mixed", R.RBF_MIXED, 1e-12), ("fp64", R.RBF_FP64, 1e-14)):
+    for tag, prec, rtol in (("mixed", R.RBF_MIXED, 1e-12), ("fp64_pc32", R.RBF_FP64_PC32, 1e-14),
+                            ("fp64", R.RBF_FP64, 1e-14)):
         out[f"c4_{tag}"] = run(w, prec, rtol)
         log("large", "c4", tag, out[f"c4_{tag}"])
     return out
@@ -528,6 +533,14 @@ def main():
         kernels["rasm_apply64"] = {
             "bound": "hbm", "achieved": bytes_ / (t_ra * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "ms": t_ra, "bytes_per_launch": bytes_}
+        # the same apply with the FP32 centre rows and FP64 sums (RBF_FP64_PC32)
+        R.rbf_precond_apply_device(h, wv, yv, R.RBF_FP64_PC32, R.RBF_ORDER_SORTED, stream)
+        t_rp = event_time(torch, stream, lambda: R.rbf_precond_apply_device(
+            h, wv, yv, R.RBF_FP64_PC32, R.RBF_ORDER_SORTED, stream), args.kernel_reps)
+        bytes32 = zbytes / 2 + 16.0 * w.n
+        kernels["rasm_apply32x64"] = {
+            "bound": "hbm", "achieved": bytes32 / (t_rp * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "ms": t_rp, "bytes_per_launch": bytes32}
     finally:
         R.rbf_destroy(h)
     # the setup's kernels one by one: HIP events the library records around
@@ -656,7 +669,8 @@ def main():
     serving = None
     if not args.no_serve:
         serving = {}
-        for tag, prec in (("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED)):
+        for tag, prec in (("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED),
+                          ("fp64_pc32", R.RBF_FP64_PC32)):
             log("serving", tag, args.serve_requests, "requests")
             serving[tag] = serving_run(R, W, args.serve_requests, prec, args.serve_active,
                                        args.serve_max_iters, packed=args.serve_engines,
