@@ -233,7 +233,7 @@ def geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, B, D, precision, reps
         t0 = time.perf_counter()
         h = R.rbf_setup_device(d_pts, d_f, w.n, w.sigma, w.cutoff, w.overlap, stream)
         try:
-            R.rbf_set_geometry(h, B, D, stream)
+            R.rbf_set_geometry(h, B, D, stream=stream)
             R.rbf_precond_setup(h, precision, stream)
             inf, st = R.rbf_solve_device(h, d_lam, opts, ok=(R.RBF_OK, R.RBF_ENOCONV))
             torch.cuda.synchronize()

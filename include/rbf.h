@@ -94,8 +94,10 @@ typedef struct {
        same figure for every solve on one handle), t_pcsetup the local
        factorisations this call made (0 if they were already built) */
     double t_init, t_pcsetup, t_matmult, t_matsolve, t_vecmdot, t_other;
-    long long interactions_per_matvec;  /* in-cutoff ordered pairs, i = j included;
-                                           -1 until rbf_neighbor_counts has run */
+    long long interactions_per_matvec;  /* in-cutoff ordered pairs, i = j included
+                                           (with a box truncation the pairs of the
+                                           box squares); -1 until rbf_neighbor_counts
+                                           has run or a truncation side was set */
     int matvecs64;          /* FP64 matvec applications in this call */
     int matvecs32;          /* FP32 matvec applications (RBF_MIXED inner solves) */
     int precond_applies;    /* RASM applications */
@@ -136,15 +138,29 @@ rbf_status rbf_set_values(rbf_problem* p, const double* values, int values_on_de
  * overlapping subdomain of a box its own points and every point within half
  * of `overlap` (D >= B) of the box's centre x_min + (b + 1/2) B along both
  * axes; members in the cell-sorted order with the box's own points last.
- * The paper's measured optimum is B = 5 sigma, D = 1.9 B.  The matvec is
- * unchanged.  Replaces the cell subdomains set up by rbf_setup (and drops any
+ * The paper's measured optimum is B = 5 sigma, D = 1.9 B.
+ * With truncation = 0 the product keeps its radial cutoff.  With a truncation
+ * side T >= B it is truncated by boxes instead (Section 3.1): a point keeps
+ * the sources inside the square of side T centred on its own box (the same
+ * |x - centre| <= T/2 test along both axes), so the matrix is no longer
+ * symmetric; the paper takes T = B + 4 sigma (B + 6 sigma at h/sigma = 0.8),
+ * which on the paper's iteration counts reads as the box widened by 4 sigma
+ * (6 sigma) on every side: T = B + 8 sigma (B + 12 sigma).  Every product,
+ * residual, count and evaluation of the handle then uses the box truncation;
+ * it runs in FP64 only (rbf_solve with RBF_MIXED and rbf_matvec_device with
+ * RBF_MIXED fail with RBF_EINVAL; RBF_FP64_PC32 is allowed), and the serving
+ * engine does not pack such handles.  A per-box list of the square's points
+ * is kept on the device (4 bytes per (box, point) pair).
+ * Replaces the cell subdomains set up by rbf_setup (and drops any
  * preconditioner built on them); rbf_precond_block then indexes boxes, row by
- * row.  Errors: RBF_EINVAL (NULL, B <= 0, D < B, non-finite, too many boxes),
- * RBF_ENOMEM; a box whose square holds more than RBF_MAX_BLOCK points makes
- * the next rbf_precond_setup fail with RBF_ELIMIT. */
+ * row.  Errors: RBF_EINVAL (NULL, B <= 0, D < B, T neither 0 nor >= B,
+ * non-finite, too many boxes), RBF_ENOMEM (the boxes may then be set with the
+ * radial product); a box whose square holds more than RBF_MAX_BLOCK points
+ * makes the next rbf_precond_setup fail with RBF_ELIMIT. */
 typedef struct {
-    double box;       /* B: side of the non-overlapping subdomains */
-    double overlap;   /* D: side of the overlapping square around each one */
+    double box;         /* B: side of the non-overlapping subdomains */
+    double overlap;     /* D: side of the overlapping square around each one */
+    double truncation;  /* T: side of the product's square per box, 0 = radial cutoff */
 } rbf_geometry;
 rbf_status rbf_set_geometry(rbf_problem* p, const rbf_geometry* geo, void* stream);
 
@@ -169,9 +185,10 @@ rbf_status rbf_solve_device(rbf_problem* p, const rbf_solve_opts* opts,
 
 /* Interpolant s(x) = sum_j lambda_j phi(|x - x_j|) (eq. rbf1 without the
  * polynomial part) at m targets (m x 2 host doubles) with the weights of the
- * last successful solve, over sources within the cutoff.  Targets outside the
- * point set's grid are clamped to the border cells.  Errors: RBF_ESTATE if no
- * solve has succeeded. */
+ * last successful solve, over sources within the cutoff (with a box
+ * truncation, over the square of the box the target falls in).  Targets
+ * outside the point set's grid are clamped to the border cells (boxes).
+ * Errors: RBF_ESTATE if no solve has succeeded. */
 rbf_status rbf_evaluate(const rbf_problem* p, const double* targets, long long m,
                         double* out);
 rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, long long m,
@@ -219,12 +236,14 @@ rbf_status rbf_grid(const rbf_problem* p, double* out4, long long* ncxy);
 rbf_status rbf_binning(const rbf_problem* p, int* cell_of, int* perm, int* cell_start);
 
 /* Number of in-cutoff sources of every point (original order, host), and the
- * total (the interactions of one matvec). */
+ * total (the interactions of one matvec); with a box truncation, the points
+ * of the square of each point's box. */
 rbf_status rbf_neighbor_counts(rbf_problem* p, int* nnb, long long* total);
 
 /* y = A w (Section 2.3, truncated normalised Gaussian) on device vectors in the
- * given order; precision RBF_MIXED runs the FP32 kernel (FP64 in and out);
- * RBF_FP64_PC32 is not a matvec precision (RBF_EINVAL). */
+ * given order; precision RBF_MIXED runs the FP32 kernel (FP64 in and out;
+ * RBF_EINVAL under a box truncation); RBF_FP64_PC32 is not a matvec precision
+ * (RBF_EINVAL). */
 rbf_status rbf_matvec_device(rbf_problem* p, const double* d_w, double* d_y,
                              rbf_precision precision, rbf_order order, void* stream);
 

@@ -76,7 +76,7 @@ _lib = None
 
 
 class Geometry(C.Structure):
-    _fields_ = [("box", C.c_double), ("overlap", C.c_double)]
+    _fields_ = [("box", C.c_double), ("overlap", C.c_double), ("truncation", C.c_double)]
 
 
 class ServerOpts(C.Structure):
@@ -311,9 +311,11 @@ def rbf_precond_apply_device(h: int, d_v, d_z, precision: int = RBF_FP64,
                                           _stream(stream)), "rbf_precond_apply_device")
 
 
-def rbf_set_geometry(h: int, box: float, overlap: float, stream=None):
-    """Subdomain boxes of side `box` with overlapping squares of side `overlap`."""
-    g = Geometry(float(box), float(overlap))
+def rbf_set_geometry(h: int, box: float, overlap: float, truncation: float = 0.0, stream=None):
+    """Subdomain boxes of side `box` with overlapping squares of side `overlap`;
+    a `truncation` side T > 0 truncates the product by the square of side T
+    around each point's box instead of the radial cutoff."""
+    g = Geometry(float(box), float(overlap), float(truncation))
     _check(lib().rbf_set_geometry(h, C.byref(g), _stream(stream)), "rbf_set_geometry")
 
 

@@ -258,6 +258,12 @@ struct rbf_problem {
     int* mem = nullptr;                // box members (sorted-order indices), own last
     long long* moff = nullptr;         // per box, offset into mem (nsub + 1)
     int* nown = nullptr;               // per box, own points
+    // box truncation of the product (truncation side T > 0 in the geometry):
+    // per box the sorted-order indices of the points of its square
+    bool boxT = false;
+    double halfT = 0;
+    int* tsrc = nullptr;
+    long long* tsoff = nullptr;
     std::vector<long long> zoff_host;
     long long* zoff = nullptr;
     int np_max = 0, nc_max = 0;
@@ -384,6 +390,20 @@ struct rbf_problem {
         a.rc2s = (float)(cutoff * cutoff * sc32 * sc32);
         a.norm = 1.0 / (2.0 * kPi * sigma * sigma);
         return a;
+    }
+    rbf::BoxTrunc bt_args() const {
+        rbf::BoxTrunc b;
+        b.bg = bg;
+        b.halfT = halfT;
+        // exp(-d2 / (2 sigma^2)) >= e^-690: the table-driven exponential's range
+        b.d2max = 1380.0 * sigma * sigma;
+        b.nbox = nsub;
+        b.src = tsrc;
+        b.soff = tsoff;
+        b.mem = mem;
+        b.moff = moff;
+        b.nown = nown;
+        return b;
     }
     rbf::PrecondArgs pc_args() const {
         rbf::PrecondArgs a;
@@ -869,6 +889,12 @@ inline rbf_precision operator_precision(rbf_precision prec) {
 rbf_status matvec(rbf_problem* p, rbf_precision prec, const double* w, double* y, hipStream_t st) {
     const bool lists = p->nl.nunits > 0;
     prec = operator_precision(prec);
+    if (p->boxT) {
+        if (prec != RBF_FP64)
+            return fail(RBF_EINVAL, "the box-truncated product runs in FP64 only");
+        HIP_TRY(rbf::launch_matvec64_box(p->mv_args(), p->bt_args(), w, y, st));
+        return RBF_OK;
+    }
     if (prec == RBF_FP64) {
         if (lists)
             HIP_TRY(rbf::launch_matvec64_lists(p->mv_args(), p->nl, w, y, st));
@@ -1144,6 +1170,9 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
     if (opts.precision != RBF_FP64 && opts.precision != RBF_MIXED &&
         opts.precision != RBF_FP64_PC32)
         return fail(RBF_EINVAL, "unknown precision");
+    if (p->boxT && opts.precision == RBF_MIXED)
+        return fail(RBF_EINVAL, "the box-truncated product runs in FP64 only: solve with "
+                                "RBF_FP64 or RBF_FP64_PC32");
     if (!p->have_values) return fail(RBF_ESTATE, "no right-hand side: pass values or call rbf_set_values");
     p->budget = opts.max_device_bytes;
     if (p->budget && p->bytes > p->budget)
@@ -1294,7 +1323,11 @@ rbf_status count_interactions(rbf_problem* p, int* d_nnb_sorted, hipStream_t st)
     long long* tot;
     RBF_TRY(p->alloc_n(&tot, 1));
     HIP_TRY(hipMemcpyAsync(y, p->fs, sizeof(double) * p->n, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(rbf::launch_matvec64(p->mv_args(), p->fs, y, d_nnb_sorted, st));
+    if (p->boxT)
+        HIP_TRY(rbf::launch_evaluate_box(p->mv_args(), p->bt_args(), p->xs, p->ys, p->n, p->fs, y,
+                                         d_nnb_sorted, st));
+    else
+        HIP_TRY(rbf::launch_matvec64(p->mv_args(), p->fs, y, d_nnb_sorted, st));
     HIP_TRY(rbf::launch_sum_counts(d_nnb_sorted, p->n, tot, st));
     long long h = 0;
     HIP_TRY(hipMemcpyAsync(&h, tot, sizeof h, hipMemcpyDeviceToHost, st));
@@ -1345,12 +1378,18 @@ rbf_status evaluate_impl(const rbf_problem* cp, const double* d_t, long long m, 
     if (d_counts) {   // the targets' in-cutoff counts: the product of the data f
         int* cnt_sorted;
         RBF_TRY(p->alloc_n(&cnt_sorted, m));
-        HIP_TRY(rbf::launch_matvec64(a, p->fs, yo, cnt_sorted, st));
+        if (p->boxT)
+            HIP_TRY(rbf::launch_evaluate_box(a, p->bt_args(), tx, ty, m, p->fs, yo, cnt_sorted, st));
+        else
+            HIP_TRY(rbf::launch_matvec64(a, p->fs, yo, cnt_sorted, st));
         HIP_TRY(rbf::launch_unpermute_int(cnt_sorted, tperm, m, d_counts, st));
         HIP_TRY(hipStreamSynchronize(st));
         p->release(cnt_sorted, st);
     } else {
-        HIP_TRY(rbf::launch_matvec64(a, p->lam, yo, nullptr, st));
+        if (p->boxT)
+            HIP_TRY(rbf::launch_evaluate_box(a, p->bt_args(), tx, ty, m, p->lam, yo, nullptr, st));
+        else
+            HIP_TRY(rbf::launch_matvec64(a, p->lam, yo, nullptr, st));
         HIP_TRY(rbf::launch_unpermute(yo, tperm, m, d_out, st));
     }
     int hflag = 0;
@@ -1954,6 +1993,7 @@ rbf_status engine_add(Engine* e, rbf_problem* p, const rbf_solve_opts& o, double
                       void* tag) {
     if (engine_active(e) >= e->cap) return fail(RBF_ELIMIT, "the engine is full");
     if (p->nl.nunits == 0) return fail(RBF_ELIMIT, "the problem has no neighbour lists");
+    if (p->boxT) return fail(RBF_ELIMIT, "box-truncated products are not packed");
     if (o.restart < 1 || o.restart > 63) return fail(RBF_EINVAL, "restart must be in [1, 63]");
     if (!p->have_values) return fail(RBF_ESTATE, "no right-hand side");
     if (o.precision != RBF_FP64 && o.precision != RBF_MIXED && o.precision != RBF_FP64_PC32)
@@ -2339,9 +2379,11 @@ rbf_status rbf_precond_block(rbf_problem* p, long long c, rbf_precision precisio
 
 rbf_status rbf_set_geometry(rbf_problem* p, const rbf_geometry* geo, void* stream) {
     if (!p || !geo) return fail(RBF_EINVAL, "NULL argument");
-    const double B = geo->box, D = geo->overlap;
+    const double B = geo->box, D = geo->overlap, T = geo->truncation;
     if (!(B > 0) || !std::isfinite(B) || !(D >= B) || !std::isfinite(D))
         return fail(RBF_EINVAL, "need 0 < box <= overlap, both finite (got %g, %g)", B, D);
+    if (!(T == 0 || (T >= B && std::isfinite(T))))
+        return fail(RBF_EINVAL, "truncation must be 0 or finite and >= box (got %g)", T);
     hipStream_t st = as_stream(stream);
     MarkOnExit mk{p, st};
     try {
@@ -2357,6 +2399,12 @@ rbf_status rbf_set_geometry(rbf_problem* p, const rbf_geometry* geo, void* strea
         if (p->mem) p->release(p->mem, st);
         if (p->moff) p->release(p->moff, st);
         if (p->nown) p->release(p->nown, st);
+        if (p->tsrc) p->release(p->tsrc, st);
+        if (p->tsoff) p->release(p->tsoff, st);
+        if (p->boxT) p->interactions = -1;   // counted again for the radial product
+        p->tsrc = nullptr;
+        p->tsoff = nullptr;
+        p->boxT = false;
         p->Z64 = nullptr;
         p->Z32 = nullptr;
         p->zoff = nullptr;
@@ -2408,6 +2456,38 @@ rbf_status rbf_set_geometry(rbf_problem* p, const rbf_geometry* geo, void* strea
         p->n_c.assign(ho.begin(), ho.end());
         p->np_max = (maxo + 63) / 64 * 64;
         p->nc_max = maxc;
+        if (T > 0) {   // the squares of the box truncation, listed per box
+            p->halfT = 0.5 * T;
+            int* ns = nullptr;
+            long long* soff = nullptr;
+            RBF_TRY(p->alloc_n(&ns, nb));
+            RBF_TRY(p->alloc_n(&soff, nb + 1));
+            rbf::BoxTrunc bt = p->bt_args();
+            const rbf::MatvecArgs ma = p->mv_args();
+            HIP_TRY(rbf::launch_box_square(ma, bt, ns, nullptr, st));
+            std::vector<int> hs(nb);
+            HIP_TRY(hipMemcpyAsync(hs.data(), ns, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            std::vector<long long> so(nb + 1, 0);
+            long long pairs = 0;
+            for (long long b = 0; b < nb; ++b) {
+                so[b + 1] = so[b] + hs[b];
+                pairs += (long long)ho[b] * hs[b];
+            }
+            int* src = nullptr;
+            RBF_TRY(p->alloc_n(&src, so[nb]));
+            HIP_TRY(hipMemcpyAsync(soff, so.data(), sizeof(long long) * (nb + 1),
+                                   hipMemcpyHostToDevice, st));
+            bt.src = src;
+            bt.soff = soff;
+            HIP_TRY(rbf::launch_box_square(ma, bt, ns, src, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            p->release(ns, st);
+            p->tsrc = src;
+            p->tsoff = soff;
+            p->boxT = true;
+            p->interactions = pairs;
+        }
         return RBF_OK;
     } catch (...) {
         return fail(RBF_ENOMEM, "host exception in rbf_set_geometry");

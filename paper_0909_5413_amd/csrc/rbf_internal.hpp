@@ -225,6 +225,35 @@ hipError_t launch_rasm_apply32(const PrecondArgs& a, const float* Z, const doubl
 hipError_t launch_rasm_apply32x64(const PrecondArgs& a, const float* Z, const double* v,
                                   double* z, hipStream_t st);
 
+// ---- box truncation of the product (boxtrunc.hip) ---------------------------
+// With subdomain boxes (Section 3.1), a target keeps the sources inside the
+// square of side T centred on its own box.  The points of box b's square are
+// src[soff[b] .. soff[b + 1]) (sorted-order indices, ascending); its targets
+// are its own points, the last nown[b] entries of mem[moff[b] .. moff[b + 1]).
+struct BoxTrunc {
+    BoxGeometry bg;
+    double halfT;
+    double d2max;           // d2 cap: keeps the exponential's argument above -690
+    long long nbox;
+    const int* src;
+    const long long* soff;
+    const int* mem;
+    const long long* moff;
+    const int* nown;
+};
+// nsrc[b] for every box (src == NULL), else the lists at src[soff[b] ..].
+hipError_t launch_box_square(const MatvecArgs& a, const BoxTrunc& bt, int* nsrc, int* src,
+                             hipStream_t st);
+// y[t] = norm * sum over the square of t's box of w[s] exp(mk d2), every point
+// t (sorted order); one workgroup per box.
+hipError_t launch_matvec64_box(const MatvecArgs& a, const BoxTrunc& bt, const double* w,
+                               double* y, hipStream_t st);
+// The same sum at m targets (tx, ty) of any position (the box by the clamped
+// box rule); nnb[i] = the size of that square, when nnb is not NULL.
+hipError_t launch_evaluate_box(const MatvecArgs& a, const BoxTrunc& bt, const double* tx,
+                               const double* ty, long long m, const double* w, double* y,
+                               int* nnb, hipStream_t st);
+
 // Batches of a handle's local factorisations in flight together (1 or 2; 2 by
 // default).  The serving loop keeps its requests to one: they already overlap
 // one another on the device, and its admission counts one batch of scratch.

@@ -1,0 +1,204 @@
+"""The box-truncated product of the paper's geometry (Section 3.1) on the GPU,
+through the C ABI (-m gpu), against the oracle with the same boxes and
+truncation side T.
+
+* Counts: every point's source count and the total pairs bit-exact (the same
+  square test in the same arithmetic), also at off-grid and clamped targets.
+* Product: element by element within 2 (k + 4) u (|A| |w|)_i, k the row's
+  source count -- both sides sum at most k terms in FP64 with different
+  orders, the exponentials within 5.2e-16 (GPU) and 1 ulp (libm) relative.
+  A square wider than the domain turns the truncation off: the product is
+  then the dense untruncated one, checked against a dense brute-force matrix.
+* Evaluation (eq. rbf1) at off-grid targets, in and outside the nodes'
+  bounding box, with the GPU's weights on both sides, to the same bar.
+* Solves: FP64 and FP64 with FP32 local inverses judged by the oracle's
+  residual of the box-truncated system, iterations within 2 of the oracle's
+  (3% beyond 67 iterations; 20% with the FP32 local inverses, whose rounding
+  changes the preconditioner); the mixed form refused; a geometry set again
+  without T restores the radial product.
+
+The cases cover a T = B square (block-diagonal products), boxes with more
+than 64 own points and squares of more than 1024 points (the kernel's passes
+over targets and over staged chunks).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_0909_5413_amd as R
+from paper_0909_5413_amd import workloads as W
+from tests import bruteforce as bf
+from tests.gates import U64, residual_gate
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.lib()
+    return torch
+
+
+def paper_case(n_side, ratio, Bs, Dr, Ts):
+    pts, sigma = W.unit_square_lattice(n_side, ratio, seed=71)
+    return pts, W.franke(pts), sigma, 6 * sigma, Bs * sigma, Dr * Bs * sigma, Ts * sigma
+
+
+def vortex_case(Bs, Dr, Ts):
+    w = W.MINI
+    pts = w.points()
+    s = w.sigma
+    return pts, w.values(pts), s, w.cutoff, Bs * s, Dr * Bs * s, Ts * s
+
+
+# T in units of sigma: the paper's B + 8 sigma (h/sigma >= 0.9) and
+# B + 12 sigma (h/sigma = 0.8), the smallest square T = B, boxes of 126
+# points with squares of about 1600, and a square wider than the domain
+CASES = {
+    "paper_0.9": lambda: paper_case(60, 0.9, 5.0, 1.9, 13.0),
+    "paper_1.0_T=B": lambda: paper_case(50, 1.0, 5.0, 1.9, 5.0),
+    "vortex_0.8": lambda: vortex_case(5.0, 1.9, 17.0),
+    "vortex_big": lambda: vortex_case(9.0, 1.5, 32.0),
+    "vortex_dense": lambda: vortex_case(5.0, 1.9, 100.0),
+}
+
+
+@pytest.fixture(scope="module")
+def problems(torch_dev, oracle_mod):
+    out = {}
+    for name, make in CASES.items():
+        pts, f, sigma, cutoff, B, D, T = make()
+        say("box truncation setup", name, pts.shape[0], "B", B / sigma, "D/B", D / B, "T", T / sigma)
+        h = R.rbf_setup(pts, f, sigma, cutoff, 1)
+        R.rbf_set_geometry(h, B, D, T)
+        P = oracle_mod.Problem(pts, sigma, cutoff, 1)
+        P.set_geometry(B, D, T)
+        out[name] = (h, P, pts, f, sigma, cutoff, B, D, T)
+    yield out
+    for v in out.values():
+        R.rbf_destroy(v[0])
+
+
+def gpu_matvec(torch, h, w, precision=R.RBF_FP64):
+    dw = torch.tensor(w, device="cuda", dtype=torch.float64)
+    dy = torch.empty_like(dw)
+    R.rbf_matvec_device(h, dw, dy, precision, R.RBF_ORDER_ORIGINAL, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return dy.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_box_counts_bit_exact(problems, name):
+    h, P, pts, *_ = problems[name]
+    nnb, tot = R.rbf_neighbor_counts(h, pts.shape[0])
+    _, o_nnb = P.matvec(np.ones(pts.shape[0]), with_counts=True)
+    say("box counts", name, "largest square", int(o_nnb.max()), "pairs", int(o_nnb.sum()))
+    assert np.array_equal(nnb, o_nnb)
+    assert tot == int(o_nnb.sum())
+    _, info, _ = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-3))
+    assert info.as_dict()["interactions_per_matvec"] == tot
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_box_matvec_elementwise(torch_dev, problems, name):
+    h, P, pts, *_ = problems[name]
+    w = W.random_weights(pts.shape[0], 72)
+    y = gpu_matvec(torch_dev, h, w)
+    yo, nnb = P.matvec(w, with_counts=True)
+    scale = P.matvec(np.abs(w))
+    bar = 2 * (nnb + 4) * U64 * scale
+    worst = float((np.abs(y - yo) / bar).max())
+    say("box matvec worst error / bar", name, worst)
+    assert np.all(np.abs(y - yo) <= bar)
+
+
+def test_box_matvec_wide_square_is_dense(torch_dev, problems):
+    """A square wider than the domain keeps every source: the dense product."""
+    h, P, pts, f, sigma, *_ = problems["vortex_dense"]
+    n = pts.shape[0]
+    w = W.random_weights(n, 73)
+    A = bf.dense_matrix(pts, sigma, None)
+    y = gpu_matvec(torch_dev, h, w)
+    bar = 2 * (n + 4) * U64 * (A @ np.abs(w))
+    assert np.all(np.abs(y - A @ w) <= bar), float((np.abs(y - A @ w) / bar).max())
+
+
+def off_grid_targets(pts, sigma, seed):
+    rng = np.random.default_rng(seed)
+    lo, hi = pts.min(axis=0), pts.max(axis=0)
+    inside = rng.uniform(lo, hi, size=(700, 2))
+    outside = rng.uniform(lo - 4 * sigma, hi + 4 * sigma, size=(300, 2))
+    return np.vstack([inside, outside])
+
+
+@pytest.mark.parametrize("name", ["paper_0.9", "vortex_0.8", "vortex_big"])
+def test_box_evaluate_and_target_counts(torch_dev, problems, name):
+    h, P, pts, f, sigma, *_ = problems[name]
+    lam, info, st = R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-10))
+    assert st == R.RBF_OK
+    tg = off_grid_targets(pts, sigma, 74)
+    s = R.rbf_evaluate(h, tg)
+    so, cnt = P.evaluate(lam, tg, with_counts=True)
+    scale = P.evaluate(np.abs(lam), tg)
+    bar = 2 * (cnt + 4) * U64 * scale
+    assert np.all(np.abs(s - so) <= bar), float((np.abs(s - so) / bar).max())
+    dt = torch_dev.tensor(tg, device="cuda", dtype=torch_dev.float64)
+    dc = torch_dev.empty(tg.shape[0], device="cuda", dtype=torch_dev.int32)
+    R.rbf_target_counts_device(h, dt, tg.shape[0], dc, torch_dev.cuda.current_stream())
+    torch_dev.cuda.synchronize()
+    assert np.array_equal(dc.cpu().numpy(), cnt)
+
+
+@pytest.mark.parametrize("name", ["paper_0.9", "paper_1.0_T=B", "vortex_0.8", "vortex_big"])
+def test_box_truncated_solves(problems, name):
+    h, P, pts, f, sigma, cutoff, B, D, T = problems[name]
+    n = pts.shape[0]
+    _, oinfo = P.gmres(f, 30, 1e-12)
+    for prec, slack in ((R.RBF_FP64, 0.03), (R.RBF_FP64_PC32, 0.2)):
+        lam, info, st = R.rbf_solve(h, n, R.default_opts(rtol=1e-12, precision=prec))
+        assert st == R.RBF_OK
+        res = P.rel_residual(f, lam)
+        say("box-T solve", name, "precision", prec, "iterations", info.iterations,
+            "oracle", oinfo.iterations, "residual", res)
+        assert info.rel_residual <= 1e-12
+        assert res <= residual_gate(P, f, lam, 1e-12), res
+        assert abs(info.iterations - oinfo.iterations) <= max(2, slack * oinfo.iterations)
+    with pytest.raises(R.RbfError) as e:
+        R.rbf_solve(h, n, R.default_opts(rtol=1e-12, precision=R.RBF_MIXED))
+    assert e.value.status == R.RBF_EINVAL
+
+
+def test_box_truncation_errors_and_reset(torch_dev, oracle_mod):
+    w = W.MINI
+    pts = w.points()
+    s = w.sigma
+    h = R.rbf_setup(pts, w.values(pts), s, w.cutoff, 1)
+    try:
+        for T in (4.0 * s, -1.0, float("inf"), float("nan")):   # T must be 0 or >= B
+            with pytest.raises(R.RbfError) as e:
+                R.rbf_set_geometry(h, 5 * s, 9.5 * s, T)
+            assert e.value.status == R.RBF_EINVAL
+        R.rbf_set_geometry(h, 5 * s, 9.5 * s, 17 * s)
+        v = W.random_weights(pts.shape[0], 75)
+        with pytest.raises(R.RbfError) as e:
+            gpu_matvec(torch_dev, h, v, R.RBF_MIXED)
+        assert e.value.status == R.RBF_EINVAL
+        # boxes again without a truncation side: the radial product
+        R.rbf_set_geometry(h, 5 * s, 9.5 * s)
+        P = oracle_mod.Problem(pts, s, w.cutoff, 1)
+        y = gpu_matvec(torch_dev, h, v)
+        yo = P.matvec(v)
+        assert np.all(np.abs(y - yo) <= 1e-13 * P.matvec(np.abs(v)))
+        nnb, tot = R.rbf_neighbor_counts(h, pts.shape[0])
+        _, o_nnb = P.matvec(np.ones(pts.shape[0]), with_counts=True)
+        assert np.array_equal(nnb, o_nnb) and tot == int(o_nnb.sum())
+    finally:
+        R.rbf_destroy(h)
