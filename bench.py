@@ -264,7 +264,35 @@ def geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, B, D, precision, reps
     return rec
 
 
-def geometry_run(R, torch, w, d_pts, d_f, d_lam, stream, sweep):
+def paper_truncation(w, B):
+    """The paper's box truncation side (Section 3.2): the box widened by 6 sigma
+    on every side at h/sigma = 0.8, by 4 sigma from 0.9 up."""
+    return B + 2 * (6.0 if w.h_over_sigma < 0.85 else 4.0) * w.sigma
+
+
+def geometry_sweep(R, torch, w, d_pts, d_f, d_lam, stream, ratios, box_t):
+    """Iterations and seconds to the workload's tolerance (FP64) over B in
+    {3, 4, 5, 6, 7} sigma and D in {1.5, 1.7, 1.9, 2.1, 2.3} B (the study of
+    Figs. 6 and 7), at each h/sigma in ratios on the same points (sigma and the
+    cutoff follow the ratio), with the radial cutoff or the paper's box
+    truncation."""
+    import dataclasses
+    rows = []
+    for r in ratios:
+        wr = dataclasses.replace(w, name=f"{w.name}_hs{r}", h_over_sigma=r)
+        for Bs in (3.0, 4.0, 5.0, 6.0, 7.0):
+            for Dr in (1.5, 1.7, 1.9, 2.1, 2.3):
+                B = Bs * wr.sigma
+                T = paper_truncation(wr, B) if box_t else 0.0
+                res = geometry_solve(R, torch, wr, d_pts, d_f, d_lam, stream, B, Dr * B,
+                                     R.RBF_FP64, reps=2, T=T)
+                rows.append({"h_over_sigma": r, "B_over_sigma": Bs, "D_over_B": Dr,
+                             "T_over_sigma": T / wr.sigma, **res})
+                log("sweep", rows[-1])
+    return rows
+
+
+def geometry_run(R, torch, w, d_pts, d_f, d_lam, stream, sweep, ratios=(), box_t=False):
     """The paper's optimum B = 5 sigma, D = 1.9 B (Section 3.2) on the
     workload, FP64 and mixed; with sweep, iterations and seconds over
     B in {3, 4, 5, 6, 7} sigma and D in {1.5, 1.7, 1.9, 2.1, 2.3} B."""
@@ -273,21 +301,13 @@ def geometry_run(R, torch, w, d_pts, d_f, d_lam, stream, sweep):
     for tag, prec in (("fp64", R.RBF_FP64), ("mixed", R.RBF_MIXED)):
         out[tag] = geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, B, 1.9 * B, prec)
         log("geometry", tag, out[tag])
-    # the paper's box truncation (Section 3.2): the box widened by 6 sigma on
-    # every side at h/sigma = 0.8, by 4 sigma from 0.9 up
-    T = B + 2 * (6.0 if w.h_over_sigma < 0.85 else 4.0) * w.sigma
+    T = paper_truncation(w, B)
     for tag, prec in (("fp64_boxT", R.RBF_FP64), ("fp64_pc32_boxT", R.RBF_FP64_PC32)):
         out[tag] = geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, B, 1.9 * B, prec, T=T)
         log("geometry", tag, out[tag])
     if sweep:
-        rows = []
-        for Bs in (3.0, 4.0, 5.0, 6.0, 7.0):
-            for Dr in (1.5, 1.7, 1.9, 2.1, 2.3):
-                r = geometry_solve(R, torch, w, d_pts, d_f, d_lam, stream, Bs * w.sigma,
-                                   Dr * Bs * w.sigma, R.RBF_FP64, reps=2)
-                rows.append({"B_over_sigma": Bs, "D_over_B": Dr, **r})
-                log("sweep", rows[-1])
-        out["sweep_fp64"] = rows
+        out["sweep_fp64" + ("_boxT" if box_t else "")] = geometry_sweep(
+            R, torch, w, d_pts, d_f, d_lam, stream, ratios or (w.h_over_sigma,), box_t)
     return out
 
 
@@ -428,6 +448,10 @@ def main():
     ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--sweep-geometry", action="store_true",
                     help="also time B in {3..7} sigma x D/B in {1.5..2.3} (Figs. 6 and 7)")
+    ap.add_argument("--sweep-ratios", type=str, default="",
+                    help="h/sigma values of the sweep, comma-separated (default: the workload's)")
+    ap.add_argument("--sweep-box-truncation", action="store_true",
+                    help="run the sweep with the paper's box truncation instead of the radial cutoff")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving stream to run (the configuration's 512)")
     ap.add_argument("--serve-active", type=int, default=8)
@@ -674,7 +698,9 @@ def main():
     # side D (its measured optimum B = 5 sigma, D = 1.9 B) against the 3x3 cells
     geometry = None
     if not args.no_geometry:
-        geometry = geometry_run(R, torch, w, d_pts, d_f, d_lam, stream, args.sweep_geometry)
+        ratios = tuple(float(v) for v in args.sweep_ratios.split(",") if v)
+        geometry = geometry_run(R, torch, w, d_pts, d_f, d_lam, stream, args.sweep_geometry,
+                                ratios, args.sweep_box_truncation)
         geometry["cells_3x3_fp64"] = {
             "s_to_tol": ms_step / 1e3, "iterations": last["iterations"],
             "z_bytes": float(np.sum(n_omega[n_c > 0].astype(np.float64) * n_c[n_c > 0])) * 8.0}

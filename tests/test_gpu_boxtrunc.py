@@ -202,3 +202,14 @@ def test_box_truncation_errors_and_reset(torch_dev, oracle_mod):
         assert np.array_equal(nnb, o_nnb) and tot == int(o_nnb.sum())
     finally:
         R.rbf_destroy(h)
+
+
+def test_box_truncated_noalloc_matches(torch_dev, problems):
+    """The allocation-free product serves a box-truncated handle bit for bit."""
+    h, P, pts, *_ = problems["vortex_0.8"]
+    w = W.random_weights(pts.shape[0], 76)
+    dw = torch_dev.tensor(w, device="cuda", dtype=torch_dev.float64)
+    dy = torch_dev.empty_like(dw)
+    R.rbf_matvec_device_noalloc(h, dw, dy, R.RBF_FP64, torch_dev.cuda.current_stream())
+    torch_dev.cuda.synchronize()
+    assert np.array_equal(dy.cpu().numpy(), gpu_matvec(torch_dev, h, w))
