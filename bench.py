@@ -215,6 +215,26 @@ def eval_run(R, torch, w, d_pts, d_f, d_lam, stream, opts):
                          "frac_r64": rate * OPS_PER_INTERACTION / VALU_OPS_PER_S,
                          "candidate_pairs": cand, "in_cutoff_share": inter / cand,
                          "candidate_pairs_per_s": cand / (ms * 1e-3)}
+        # the same staggered lattice through the lattice entry point (targets
+        # x0 + a h, the cells' shared 3x3 blocks and separable factors)
+        n1, hh = w.n_side - 1, w.h
+        x0l = -1.0 + hh
+        ax = x0l + np.arange(n1, dtype=np.float64) * hh
+        gx, gy = np.meshgrid(ax, ax, indexing="xy")
+        tg = np.ascontiguousarray(np.stack([gx.ravel(), gy.ravel()], axis=1))
+        m = tg.shape[0]
+        d_t = torch.tensor(tg, device=d_pts.device)
+        d_c = torch.empty(m, device=d_pts.device, dtype=torch.int32)
+        R.rbf_target_counts_device(h, d_t, m, d_c, stream)
+        inter = int(d_c.to(torch.int64).sum().item())
+        d_s = torch.empty(m, device=d_pts.device, dtype=torch.float64)
+        ms = event_median(torch, stream, lambda: R.rbf_evaluate_lattice_device(
+            h, x0l, x0l, hh, hh, n1, n1, d_s, stream), 3, 20)
+        rate = inter / (ms * 1e-3)
+        out["staggered_lattice_separable"] = {
+            "targets": m, "ms": ms, "evaluations_per_s": m / (ms * 1e-3), "interactions": inter,
+            "interactions_per_s": rate, "frac_r64": rate * OPS_PER_INTERACTION / VALU_OPS_PER_S,
+            "speedup_vs_targets": out["staggered_lattice"]["ms"] / ms}
     finally:
         R.rbf_destroy(h)
     return out

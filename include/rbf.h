@@ -194,6 +194,22 @@ rbf_status rbf_evaluate(const rbf_problem* p, const double* targets, long long m
 rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, long long m,
                                double* d_out, void* stream);
 
+/* The interpolant on a regular lattice of targets, t(a, b) = (x0 + a hx,
+ * y0 + b hy) for a < nx, b < ny (remeshing onto a lattice, the use the paper's
+ * Sections 1 and 5 name): out[b nx + a], the same sums as rbf_evaluate at those
+ * coordinates (each computed as x0 + a * hx, one rounding per operation), with
+ * the lattice's separable structure used for speed.  hx, hy > 0; x0, y0 and the
+ * far corner finite.  out: nx * ny doubles, host (rbf_evaluate_lattice) or
+ * device on `stream` (rbf_evaluate_lattice_device), caller-owned.  nx or ny = 0
+ * writes nothing.  Errors: RBF_ESTATE (no successful solve), RBF_EINVAL (NULL
+ * output, negative sizes, non-finite origin or extent, spacing <= 0),
+ * RBF_ELIMIT (a side above 2^31 or more than 2^40 targets), RBF_ENOMEM. */
+rbf_status rbf_evaluate_lattice(const rbf_problem* p, double x0, double y0, double hx, double hy,
+                                long long nx, long long ny, double* out);
+rbf_status rbf_evaluate_lattice_device(const rbf_problem* p, double x0, double y0, double hx,
+                                       double hy, long long nx, long long ny, double* d_out,
+                                       void* stream);
+
 /* The number of sources the interpolant sums at each of m targets (device
  * arrays: targets m x 2, counts m ints, original target order): the in-cutoff
  * neighbours of eq. rbf1's truncated sum, found as rbf_evaluate_device finds

@@ -27,7 +27,8 @@ RBF_NOALLOC_MAX_POINTS = 4194304
 EXPORTED = [
     "rbf_default_opts", "rbf_setup", "rbf_setup_device", "rbf_set_values",
     "rbf_precond_setup", "rbf_solve", "rbf_solve_device", "rbf_evaluate",
-    "rbf_evaluate_device", "rbf_target_counts_device", "rbf_destroy", "rbf_block_cache", "rbf_grid", "rbf_binning",
+    "rbf_evaluate_device", "rbf_evaluate_lattice", "rbf_evaluate_lattice_device",
+    "rbf_target_counts_device", "rbf_destroy", "rbf_block_cache", "rbf_grid", "rbf_binning",
     "rbf_neighbor_counts", "rbf_matvec_device", "rbf_matvec_device_noalloc",
     "rbf_precond_apply_device",
     "rbf_precond_block", "rbf_set_geometry", "rbf_set_profiling", "rbf_set_graphs", "rbf_setup_kernel_times",
@@ -113,6 +114,11 @@ def lib():
         "rbf_solve_device": (C.c_int, [vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveInfo)]),
         "rbf_evaluate": (C.c_int, [vp, vp, C.c_longlong, vp]),
         "rbf_evaluate_device": (C.c_int, [vp, vp, C.c_longlong, vp, vp]),
+        "rbf_evaluate_lattice": (C.c_int, [vp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.c_longlong, C.c_longlong, vp]),
+        "rbf_evaluate_lattice_device": (C.c_int, [vp, C.c_double, C.c_double, C.c_double,
+                                                  C.c_double, C.c_longlong, C.c_longlong, vp,
+                                                  vp]),
         "rbf_target_counts_device": (C.c_int, [vp, vp, C.c_longlong, vp, vp]),
         "rbf_destroy": (None, [vp]),
         "rbf_block_cache": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
@@ -251,6 +257,22 @@ def rbf_evaluate(h: int, targets) -> np.ndarray:
 def rbf_evaluate_device(h: int, d_targets, m: int, d_out, stream=None):
     _check(lib().rbf_evaluate_device(h, _ptr(d_targets), m, _ptr(d_out), _stream(stream)),
            "rbf_evaluate_device")
+
+
+def rbf_evaluate_lattice(h: int, x0: float, y0: float, hx: float, hy: float, nx: int,
+                         ny: int) -> np.ndarray:
+    """The interpolant at (x0 + a hx, y0 + b hy), a < nx, b < ny, as an
+    (ny, nx) array (row b, column a)."""
+    out = np.empty((max(ny, 0), max(nx, 0)))
+    _check(lib().rbf_evaluate_lattice(h, x0, y0, hx, hy, nx, ny, _ptr(out)),
+           "rbf_evaluate_lattice")
+    return out
+
+
+def rbf_evaluate_lattice_device(h: int, x0: float, y0: float, hx: float, hy: float, nx: int,
+                                ny: int, d_out, stream=None):
+    _check(lib().rbf_evaluate_lattice_device(h, x0, y0, hx, hy, nx, ny, _ptr(d_out),
+                                             _stream(stream)), "rbf_evaluate_lattice_device")
 
 
 def rbf_target_counts_device(h: int, d_targets, m: int, d_counts, stream=None):

@@ -16,8 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librbf_hip.so")
 OBJ = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["binning.hip", "matvec.hip", "boxtrunc.hip", "precond.hip", "krylov.hip", "noalloc.hip",
-           "capi.cpp", "server.cpp"]
+SOURCES = ["binning.hip", "matvec.hip", "boxtrunc.hip", "lattice.hip", "precond.hip", "krylov.hip",
+           "noalloc.hip", "capi.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RBF_OFFLOAD_ARCH", "gfx950")

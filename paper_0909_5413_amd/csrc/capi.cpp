@@ -2177,6 +2177,136 @@ rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, lo
     }
 }
 
+namespace {
+
+// cell coordinate of v along one axis: the binning's rule (floor((v - v0) / L)
+// by the stored reciprocal, clamped), the arithmetic of every kernel
+int axis_cell(double v, double v0, double invL, int n) {
+    double t = std::floor((v - v0) * invL);
+    if (!(t >= 0.0)) t = 0.0;
+    if (t > (double)(n - 1)) t = (double)(n - 1);
+    return (int)t;
+}
+
+// Lattice indices 0 .. n-1 of one axis (coordinate v0 + i hv) grouped by cell
+// (the rule is monotone in i for hv > 0), each run cut into chunks of at most
+// kLatticeChunk.
+void lattice_chunks(double v0, double hv, long long n, double g0, double invL, int nc,
+                    std::vector<rbf::LatticeChunk>* out) {
+    long long i = 0;
+    while (i < n) {
+        const int c = axis_cell(v0 + (double)i * hv, g0, invL, nc);
+        long long e = i + 1;
+        while (e < n && axis_cell(v0 + (double)e * hv, g0, invL, nc) == c) ++e;
+        for (long long t = i; t < e; t += rbf::kLatticeChunk)
+            out->push_back({t, c, (int)std::min<long long>(rbf::kLatticeChunk, e - t)});
+        i = e;
+    }
+}
+
+// RBF_OK with nothing to do for an empty lattice (*empty set), else the
+// argument checks of both lattice entry points
+rbf_status check_lattice(const rbf_problem* p, double x0, double y0, double hx, double hy,
+                         long long nx, long long ny, const double* out, bool* empty) {
+    *empty = true;
+    if (!p->solved || !p->lam) return fail(RBF_ESTATE, "evaluate needs a successful solve first");
+    if (nx < 0 || ny < 0) return fail(RBF_EINVAL, "negative lattice size");
+    if (nx == 0 || ny == 0) return RBF_OK;
+    if (!out) return fail(RBF_EINVAL, "NULL output");
+    if (!(hx > 0) || !(hy > 0) || !std::isfinite(x0) || !std::isfinite(y0) ||
+        !std::isfinite(x0 + (double)(nx - 1) * hx) || !std::isfinite(y0 + (double)(ny - 1) * hy))
+        return fail(RBF_EINVAL, "lattice: need finite origin and spacings > 0 with finite extent");
+    if (nx > (1LL << 31) || ny > (1LL << 31) || nx * ny > (1LL << 40))
+        return fail(RBF_ELIMIT, "lattice of %lld x %lld targets", nx, ny);
+    *empty = false;
+    return RBF_OK;
+}
+
+rbf_status evaluate_lattice_impl(const rbf_problem* cp, double x0, double y0, double hx, double hy,
+                                 long long nx, long long ny, double* d_out, hipStream_t st) {
+    rbf_problem* p = const_cast<rbf_problem*>(cp);
+    rbf::LatticeArgs L{};
+    L.x0 = x0;
+    L.y0 = y0;
+    L.hx = hx;
+    L.hy = hy;
+    L.nx = nx;
+    if (p->boxT) {   // the box truncation takes target arrays
+        const long long m = nx * ny;
+        double *tx, *ty;
+        RBF_TRY(p->alloc_n(&tx, m));
+        RBF_TRY(p->alloc_n(&ty, m));
+        HIP_TRY(rbf::launch_lattice_points(L, ny, tx, ty, st));
+        HIP_TRY(rbf::launch_evaluate_box(p->mv_args(), p->bt_args(), tx, ty, m, p->lam, d_out,
+                                         nullptr, st));
+        p->release(tx, st);
+        p->release(ty, st);
+        return RBF_OK;
+    }
+    std::vector<rbf::LatticeChunk> col, row;
+    lattice_chunks(x0, hx, nx, p->g.x0, p->g.invL, p->g.ncx, &col);
+    lattice_chunks(y0, hy, ny, p->g.y0, p->g.invL, p->g.ncy, &row);
+    if ((long long)col.size() * (long long)row.size() > 0x7fffffffLL)
+        return fail(RBF_ELIMIT, "lattice needs %zu x %zu chunks", col.size(), row.size());
+    rbf::LatticeChunk *dcol, *drow;
+    RBF_TRY(p->alloc_n(&dcol, (long long)col.size()));
+    RBF_TRY(p->alloc_n(&drow, (long long)row.size()));
+    HIP_TRY(hipMemcpyAsync(dcol, col.data(), sizeof(rbf::LatticeChunk) * col.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(drow, row.data(), sizeof(rbf::LatticeChunk) * row.size(),
+                           hipMemcpyHostToDevice, st));
+    L.col = dcol;
+    L.row = drow;
+    L.ncol = (int)col.size();
+    L.nrow = (int)row.size();
+    HIP_TRY(rbf::launch_evaluate_lattice(p->mv_args(), L, p->lam, d_out, st));
+    // the chunk tables are host vectors: wait for the copies before they go
+    HIP_TRY(hipStreamSynchronize(st));
+    p->release(dcol, st);
+    p->release(drow, st);
+    return RBF_OK;
+}
+
+}  // namespace
+
+rbf_status rbf_evaluate_lattice(const rbf_problem* p, double x0, double y0, double hx, double hy,
+                                long long nx, long long ny, double* out) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    bool empty;
+    RBF_TRY(check_lattice(p, x0, y0, hx, hy, nx, ny, out, &empty));
+    if (empty) return RBF_OK;
+    try {
+        MarkOnExit mk{p, nullptr};
+        rbf_problem* q = const_cast<rbf_problem*>(p);
+        double* dout;
+        RBF_TRY(q->alloc_n(&dout, nx * ny));
+        rbf_status s = evaluate_lattice_impl(p, x0, y0, hx, hy, nx, ny, dout, nullptr);
+        if (s == RBF_OK) {
+            hipError_t e = hipMemcpy(out, dout, sizeof(double) * nx * ny, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) s = fail(RBF_EDEVICE, "copy out: %s", hipGetErrorString(e));
+        }
+        q->release(dout, nullptr);
+        return s;
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_evaluate_lattice");
+    }
+}
+
+rbf_status rbf_evaluate_lattice_device(const rbf_problem* p, double x0, double y0, double hx,
+                                       double hy, long long nx, long long ny, double* d_out,
+                                       void* stream) {
+    if (!p) return fail(RBF_EINVAL, "NULL problem");
+    bool empty;
+    RBF_TRY(check_lattice(p, x0, y0, hx, hy, nx, ny, d_out, &empty));
+    if (empty) return RBF_OK;
+    try {
+        MarkOnExit mk{p, as_stream(stream)};
+        return evaluate_lattice_impl(p, x0, y0, hx, hy, nx, ny, d_out, as_stream(stream));
+    } catch (...) {
+        return fail(RBF_ENOMEM, "host exception in rbf_evaluate_lattice_device");
+    }
+}
+
 rbf_status rbf_target_counts_device(const rbf_problem* p, const double* d_targets, long long m,
                                     int* d_counts, void* stream) {
     if (!p) return fail(RBF_EINVAL, "NULL problem");

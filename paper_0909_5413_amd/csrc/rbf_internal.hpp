@@ -254,6 +254,33 @@ hipError_t launch_evaluate_box(const MatvecArgs& a, const BoxTrunc& bt, const do
                                const double* ty, long long m, const double* w, double* y,
                                int* nnb, hipStream_t st);
 
+// ---- evaluation on a regular lattice of targets (lattice.hip) ---------------
+// Targets (x0 + a hx, y0 + b hy), a < nx, b < ny, output at b nx + a.  Along
+// each axis the lattice indices are grouped by the cell the cell rule gives
+// their coordinate (a contiguous run, the rule being monotone) and cut into
+// chunks of at most kLatticeChunk; one wave serves each (column chunk, row
+// chunk) pair, workgroup i + ncol j for column chunk i and row chunk j.
+constexpr int kLatticeChunk = 8;
+struct LatticeChunk {
+    long long t0;            // first lattice index
+    int c;                   // the cell column (row) of all of them
+    int nt;                  // indices in the chunk, 1 .. kLatticeChunk
+};
+struct LatticeArgs {
+    double x0, y0, hx, hy;
+    long long nx;
+    const LatticeChunk* col;
+    const LatticeChunk* row;
+    int ncol, nrow;
+};
+// out[b nx + a] = norm * sum over the target's 3x3 block of w[s] exp(mk d2),
+// d2 <= rc2 (the cell-binned product at lattice targets)
+hipError_t launch_evaluate_lattice(const MatvecArgs& a, const LatticeArgs& L, const double* w,
+                                   double* out, hipStream_t st);
+// the lattice's coordinates, target b nx + a at tx[b nx + a], ty[b nx + a]
+hipError_t launch_lattice_points(const LatticeArgs& L, long long ny, double* tx, double* ty,
+                                 hipStream_t st);
+
 // Batches of a handle's local factorisations in flight together (1 or 2; 2 by
 // default).  The serving loop keeps its requests to one: they already overlap
 // one another on the device, and its admission counts one batch of scratch.
