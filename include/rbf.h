@@ -154,9 +154,10 @@ rbf_status rbf_set_values(rbf_problem* p, const double* values, int values_on_de
  * Replaces the cell subdomains set up by rbf_setup (and drops any
  * preconditioner built on them); rbf_precond_block then indexes boxes, row by
  * row.  Errors: RBF_EINVAL (NULL, B <= 0, D < B, T neither 0 nor >= B,
- * non-finite, too many boxes), RBF_ENOMEM (the boxes may then be set with the
- * radial product); a box whose square holds more than RBF_MAX_BLOCK points
- * makes the next rbf_precond_setup fail with RBF_ELIMIT. */
+ * non-finite, too many boxes), RBF_ELIMIT (a truncation side with 2^24 boxes
+ * or more), RBF_ENOMEM (the boxes may then be set with the radial product); a
+ * box whose square holds more than RBF_MAX_BLOCK points makes the next
+ * rbf_precond_setup fail with RBF_ELIMIT. */
 typedef struct {
     double box;         /* B: side of the non-overlapping subdomains */
     double overlap;     /* D: side of the overlapping square around each one */
@@ -203,7 +204,8 @@ rbf_status rbf_evaluate_device(const rbf_problem* p, const double* d_targets, lo
  * device on `stream` (rbf_evaluate_lattice_device), caller-owned.  nx or ny = 0
  * writes nothing.  Errors: RBF_ESTATE (no successful solve), RBF_EINVAL (NULL
  * output, negative sizes, non-finite origin or extent, spacing <= 0),
- * RBF_ELIMIT (a side above 2^31 or more than 2^40 targets), RBF_ENOMEM. */
+ * RBF_ELIMIT (a side above 2^31, more than 2^40 targets, or more than 2^26
+ * tiles of 8 x 8 targets within one cell each), RBF_ENOMEM. */
 rbf_status rbf_evaluate_lattice(const rbf_problem* p, double x0, double y0, double hx, double hy,
                                 long long nx, long long ny, double* out);
 rbf_status rbf_evaluate_lattice_device(const rbf_problem* p, double x0, double y0, double hx,

@@ -2246,8 +2246,10 @@ rbf_status evaluate_lattice_impl(const rbf_problem* cp, double x0, double y0, do
     std::vector<rbf::LatticeChunk> col, row;
     lattice_chunks(x0, hx, nx, p->g.x0, p->g.invL, p->g.ncx, &col);
     lattice_chunks(y0, hy, ny, p->g.y0, p->g.invL, p->g.ncy, &row);
-    if ((long long)col.size() * (long long)row.size() > 0x7fffffffLL)
-        return fail(RBF_ELIMIT, "lattice needs %zu x %zu chunks", col.size(), row.size());
+    // one 64-thread workgroup per chunk pair, at most 2^32 - 1 threads per launch
+    if ((long long)col.size() * (long long)row.size() > (1LL << 26) - 1)
+        return fail(RBF_ELIMIT, "lattice needs %zu x %zu chunks of 8 x 8 targets (at most 2^26)",
+                    col.size(), row.size());
     rbf::LatticeChunk *dcol, *drow;
     RBF_TRY(p->alloc_n(&dcol, (long long)col.size()));
     RBF_TRY(p->alloc_n(&drow, (long long)row.size()));
@@ -2587,6 +2589,9 @@ rbf_status rbf_set_geometry(rbf_problem* p, const rbf_geometry* geo, void* strea
         p->np_max = (maxo + 63) / 64 * 64;
         p->nc_max = maxc;
         if (T > 0) {   // the squares of the box truncation, listed per box
+            // one 256-thread workgroup per box, at most 2^32 - 1 threads per launch
+            if (nb > (1LL << 24) - 1)
+                return fail(RBF_ELIMIT, "box truncation over %lld boxes (at most 2^24 - 1)", nb);
             p->halfT = 0.5 * T;
             int* ns = nullptr;
             long long* soff = nullptr;
