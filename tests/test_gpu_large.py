@@ -218,6 +218,86 @@ def test_c1_bench_workload(torch_dev, oracle_mod):
 
 
 @pytest.mark.timeout(300)
+def test_c1_box_truncation_and_lattice(torch_dev, oracle_mod):
+    """The paper's geometry and remeshing at the benchmarked size (N = 10^6,
+    h/sigma = 0.8): with boxes B = 5 sigma, D = 1.9 B and the box truncation
+    T = B + 12 sigma, every point's source count bit-exact against the oracle
+    and the whole box-truncated product element by element within
+    2 (k + 4) u (|A| |w|)_i; then, on a radial handle solved to 1e-12, the
+    interpolant on the 999 x 999 staggered lattice through the lattice entry
+    point, against the oracle on 20,000 sampled targets within
+    2 (k + 40) u (|A| |lambda|)_i, and against the arbitrary-target path on all
+    of them within the same bar with (|A| |lambda|)_i bounded by
+    k_max max|lambda| phi(0)."""
+    torch = torch_dev
+    w = W.WORKLOADS["c1"]
+    pts = w.points()
+    f = w.values(pts)
+    d_pts = torch.tensor(pts, device="cuda")
+    d_f = torch.tensor(f, device="cuda")
+    st = torch.cuda.current_stream()
+    u = 2.0 ** -53
+    s = w.sigma
+    B, D, T = 5 * s, 9.5 * s, 17 * s
+    P = oracle_mod.Problem(pts, s, w.cutoff, w.overlap)
+    P.set_geometry(B, D, T)
+    h = R.rbf_setup_device(d_pts, d_f, w.n, s, w.cutoff, w.overlap, st)
+    try:
+        R.rbf_set_geometry(h, B, D, T, stream=st)
+        nnb, tot = R.rbf_neighbor_counts(h, w.n)
+        wv = W.random_weights(w.n, 23)
+        yo, o_nnb = P.matvec(wv, with_counts=True)
+        assert np.array_equal(nnb, o_nnb)
+        assert tot == int(o_nnb.astype(np.int64).sum())
+        d_w = torch.tensor(wv, device="cuda")
+        d_y = torch.empty_like(d_w)
+        R.rbf_matvec_device(h, d_w, d_y, R.RBF_FP64, R.RBF_ORDER_ORIGINAL, st)
+        torch.cuda.synchronize()
+        scale = P.matvec(np.abs(wv))
+        bar = 2 * (o_nnb + 4) * u * scale
+        err = np.abs(d_y.cpu().numpy() - yo)
+        say("c1 box truncation: pairs", tot, "worst error / bar", float((err / bar).max()))
+        assert np.all(err <= bar)
+    finally:
+        R.rbf_destroy(h)
+    P.close()
+    h = R.rbf_setup_device(d_pts, d_f, w.n, s, w.cutoff, w.overlap, st)
+    try:
+        lam = torch.empty(w.n, device="cuda", dtype=torch.float64)
+        info, status = R.rbf_solve_device(h, lam, R.default_opts(rtol=1e-12, stream=st))
+        assert status == R.RBF_OK
+        n1, hh = w.n_side - 1, w.h
+        x0 = -1.0 + hh
+        d_out = torch.empty(n1 * n1, device="cuda", dtype=torch.float64)
+        R.rbf_evaluate_lattice_device(h, x0, x0, hh, hh, n1, n1, d_out, st)
+        ax = x0 + np.arange(n1, dtype=np.float64) * hh
+        gx, gy = np.meshgrid(ax, ax, indexing="xy")
+        tg = np.ascontiguousarray(np.stack([gx.ravel(), gy.ravel()], axis=1))
+        d_t = torch.tensor(tg, device="cuda")
+        d_ref = torch.empty_like(d_out)
+        R.rbf_evaluate_device(h, d_t, tg.shape[0], d_ref, st)
+        torch.cuda.synchronize()
+        out, ref, lam_h = d_out.cpu().numpy(), d_ref.cpu().numpy(), lam.cpu().numpy()
+        Po = oracle_mod.Problem(pts, s, w.cutoff, w.overlap)
+        rows = np.random.default_rng(24).choice(tg.shape[0], 20000, replace=False)
+        so, cnt = Po.evaluate(lam_h, tg[rows], with_counts=True)
+        sc = Po.evaluate(np.abs(lam_h), tg[rows])
+        bar = 2 * (cnt + 40) * u * sc
+        say("c1 lattice: worst sampled error / bar", float((np.abs(out[rows] - so) / bar).max()))
+        assert np.all(np.abs(out[rows] - so) <= bar)
+        # every target against the arbitrary-target path; the counts bound k
+        d_c = torch.empty(tg.shape[0], device="cuda", dtype=torch.int32)
+        R.rbf_target_counts_device(h, d_t, tg.shape[0], d_c, st)
+        torch.cuda.synchronize()
+        kmax = int(d_c.max().item())
+        amax = float(np.abs(lam_h).max())
+        bound_all = 2 * (kmax + 40) * u * kmax * amax / (2 * np.pi * s * s)
+        assert np.max(np.abs(out - ref)) <= bound_all
+    finally:
+        R.rbf_destroy(h)
+
+
+@pytest.mark.timeout(300)
 def test_two_batches_in_flight_match_one(torch_dev):
     """The local factorisations run two batches at once on two streams when a
     problem has several batches; the profiled setup runs one at a time.  Both
