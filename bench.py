@@ -81,12 +81,14 @@ def profiled_traffic(kernel):
     return None
 
 
-def serving_run(R, W, k, precision, max_active, max_iters, packed=2, n_hi=1e6):
+def serving_run(R, W, k, precision, max_active, max_iters, packed=2, n_hi=1e6, stall_cycles=0):
     """The request stream of the serving configuration through rbf_server_*:
     a closed-loop run (all k requests submitted at once) measures the capacity
     in solves/s, then an open-loop run submits the same requests at Poisson
     arrival times with 0.7x that rate and records each request's latency
-    (submission to completion, the server's steady clock)."""
+    (submission to completion, the server's steady clock).  stall_cycles > 0
+    lets the FP64 solves give up on a stagnating system (the library's
+    stall stop); the mixed form has its own stop."""
     import numpy as np
     reqs = W.serving_requests(k, n_hi=n_hi)
     data = []
@@ -97,7 +99,8 @@ def serving_run(R, W, k, precision, max_active, max_iters, packed=2, n_hi=1e6):
     def submit(srv, w, p, f):
         return R.rbf_server_submit(srv, p, f, w.sigma, w.cutoff, w.overlap,
                                    R.default_opts(rtol=w.rtol, precision=precision,
-                                                  max_iters=max_iters))
+                                                  max_iters=max_iters,
+                                                  stall_cycles=stall_cycles))
 
     everything = tuple(range(11))
     srv = R.rbf_server_create(max_active=max_active, packed=packed)
@@ -132,6 +135,7 @@ def serving_run(R, W, k, precision, max_active, max_iters, packed=2, n_hi=1e6):
         "precision": {R.RBF_FP64: "fp64", R.RBF_MIXED: "mixed"}.get(precision, "fp64_pc32"),
         "mode": f"{packed} packed engines" if packed else "one stream per request",
         "max_active": max_active, "max_iters": max_iters, "n_hi": n_hi,
+        "stall_cycles": stall_cycles if precision != R.RBF_MIXED else None,
         "converged_latency_p50_s": float(np.percentile(conv, 50)) if conv.size else None,
         "converged_latency_p99_s": float(np.percentile(conv, 99)) if conv.size else None,
         "capacity_solves_per_s": cap, "offered_rate_per_s": rate,
@@ -476,6 +480,9 @@ def main():
                     help="requests of the serving stream to run (the configuration's 512)")
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-max-iters", type=int, default=300)
+    ap.add_argument("--serve-stall-cycles", type=int, default=0,
+                    help="FP64 requests end once the residual has not halved in this many "
+                         "GMRES cycles (0: off; otherwise the FP64 stream also runs without it)")
     ap.add_argument("--serve-engines", type=int, default=2,
                     help="packed engines of the server (0: one stream per request)")
     ap.add_argument("--serve-n-hi", type=float, default=1e6,
@@ -734,8 +741,14 @@ def main():
             log("serving", tag, args.serve_requests, "requests")
             serving[tag] = serving_run(R, W, args.serve_requests, prec, args.serve_active,
                                        args.serve_max_iters, packed=args.serve_engines,
-                                       n_hi=args.serve_n_hi)
+                                       n_hi=args.serve_n_hi,
+                                       stall_cycles=args.serve_stall_cycles)
             log("serving", tag, serving[tag])
+            if prec == R.RBF_FP64 and args.serve_stall_cycles:   # the same stream without it
+                serving["fp64_no_stall_stop"] = serving_run(
+                    R, W, args.serve_requests, prec, args.serve_active, args.serve_max_iters,
+                    packed=args.serve_engines, n_hi=args.serve_n_hi)
+                log("serving", "fp64_no_stall_stop", serving["fp64_no_stall_stop"])
             for e in (int(v) for v in args.serve_compare.split(",") if v.strip()):
                 serving[f"{tag}_engines{e}"] = serving_run(R, W, args.serve_requests, prec,
                                                            args.serve_active, args.serve_max_iters,

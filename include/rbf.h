@@ -82,6 +82,14 @@ typedef struct {
                                undone and the solve ends with RBF_ENOCONV */
     size_t max_device_bytes;/* 0 = no limit; else fail with RBF_ENOMEM beyond it */
     void* stream;           /* hipStream_t for every launch of the call */
+    int stall_cycles;       /* RBF_FP64 and RBF_FP64_PC32: 0 (default) = off; k > 0 ends
+                               the solve with RBF_ENOCONV (and its last iterate) when
+                               the true residual at the start of a cycle is above half
+                               of what it was k cycles earlier -- for callers such as a
+                               serving loop that would rather give up on a stagnating
+                               system (GMRES(m) restarted on a system beyond the
+                               preconditioner, e.g. h/sigma < 0.7 with the 6 sigma
+                               cutoff) than spend max_iters on it */
 } rbf_solve_opts;
 
 typedef struct {

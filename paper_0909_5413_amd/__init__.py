@@ -8,6 +8,7 @@ there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import importlib.util
 import os
 from dataclasses import dataclass
 
@@ -53,7 +54,8 @@ class RbfError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("rtol", C.c_double),
                 ("precision", C.c_int), ("inner_rtol", C.c_double), ("max_outer", C.c_int),
-                ("max_device_bytes", C.c_size_t), ("stream", C.c_void_p)]
+                ("max_device_bytes", C.c_size_t), ("stream", C.c_void_p),
+                ("stall_cycles", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -100,6 +102,13 @@ def lib():
         raise RbfLibraryMissing(
             f"{LIB_PATH} not found: build it with `python -m paper_0909_5413_amd.build` "
             "(there is no CPU fallback)")
+    # PyTorch ships its own HIP runtime under the same soname as the system's,
+    # and whichever loads first serves the whole process.  If this library
+    # brought in the system runtime and PyTorch then initialised its device,
+    # the library's later HIP calls would find no device; loading PyTorch
+    # first (when it is installed) gives one runtime in either import order.
+    if importlib.util.find_spec("torch") is not None:
+        import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, dp, ip, lp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_longlong)
     pp = C.POINTER(C.c_void_p)

@@ -427,6 +427,16 @@ struct rbf_problem {
 };
 
 namespace rbf {
+rbf_status set_error(rbf_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
 void set_setup_lanes(rbf_problem* p, int lanes) {
     if (p) p->setup_lanes = lanes > 1 ? 2 : 1;
 }
@@ -1144,6 +1154,13 @@ rbf_status gmres_cycles(rbf_problem* p, rbf_precision prec, const double* b, dou
 
 rbf_status count_interactions(rbf_problem* p, int* d_nnb_sorted, hipStream_t st);
 
+// The stagnation stop of the FP64 solves: the cycle-start true residuals in
+// history (the last one the current), k > 0 cycles back.
+bool stalled(const std::vector<double>& history, int k) {
+    const size_t n = history.size();
+    return k > 0 && n > (size_t)k && history[n - 1] > 0.5 * history[n - 1 - (size_t)k];
+}
+
 rbf_status true_rel_residual(rbf_problem* p, const double* b, const double* x, double bnorm,
                              double* rel, hipStream_t st, PhaseTimes* pt) {
     HIP_TRY(hipEventRecord(p->pev[0], st));
@@ -1167,6 +1184,7 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
     if (opts.restart < 1 || opts.restart > 63) return fail(RBF_EINVAL, "restart must be in [1, 63]");
     if (!(opts.rtol >= 0)) return fail(RBF_EINVAL, "rtol must be >= 0");
     if (opts.max_iters < 0) return fail(RBF_EINVAL, "max_iters must be >= 0");
+    if (opts.stall_cycles < 0) return fail(RBF_EINVAL, "stall_cycles must be >= 0");
     if (opts.precision != RBF_FP64 && opts.precision != RBF_MIXED &&
         opts.precision != RBF_FP64_PC32)
         return fail(RBF_EINVAL, "unknown precision");
@@ -1224,6 +1242,12 @@ rbf_status solve_impl(rbf_problem* p, const rbf_solve_opts* o, const double* d_l
             if (iters >= opts.max_iters) {
                 status = fail(RBF_ENOCONV, "no convergence in %d iterations (rel. residual %.3e)",
                               iters, rel);
+                break;
+            }
+            if (stalled(p->history, opts.stall_cycles)) {
+                status = fail(RBF_ENOCONV, "stalled: residual %.3e after %d iterations, above "
+                                           "half its value %d cycles earlier",
+                              rel, iters, opts.stall_cycles);
                 break;
             }
             CycleResult cr;
@@ -1745,6 +1769,14 @@ public:
             s = RBF_OK;
         } else if (!q.mixed && q.iters >= q.o.max_iters) {
             s = RBF_ENOCONV;
+        } else if (!q.mixed && stalled(p->history, q.o.stall_cycles)) {
+            char buf[160];
+            snprintf(buf, sizeof buf,
+                     "stalled: residual %.3e after %d iterations, above half its value %d cycles "
+                     "earlier",
+                     q.rel, q.iters, q.o.stall_cycles);
+            finish(q, done, RBF_ENOCONV, buf);
+            return false;
         } else if (q.mixed && (q.outer >= q.o.max_outer || q.iters >= q.o.max_iters)) {
             s = RBF_ENOCONV;
         } else {
@@ -1995,6 +2027,7 @@ rbf_status engine_add(Engine* e, rbf_problem* p, const rbf_solve_opts& o, double
     if (p->nl.nunits == 0) return fail(RBF_ELIMIT, "the problem has no neighbour lists");
     if (p->boxT) return fail(RBF_ELIMIT, "box-truncated products are not packed");
     if (o.restart < 1 || o.restart > 63) return fail(RBF_EINVAL, "restart must be in [1, 63]");
+    if (o.stall_cycles < 0) return fail(RBF_EINVAL, "stall_cycles must be >= 0");
     if (!p->have_values) return fail(RBF_ESTATE, "no right-hand side");
     if (o.precision != RBF_FP64 && o.precision != RBF_MIXED && o.precision != RBF_FP64_PC32)
         return fail(RBF_EINVAL, "unknown precision");
@@ -2051,6 +2084,7 @@ void rbf_default_opts(rbf_solve_opts* o) {
     o->max_outer = 60;
     o->max_device_bytes = 0;
     o->stream = nullptr;
+    o->stall_cycles = 0;
 }
 
 rbf_status rbf_setup(const double* points, const double* values, long long n, double sigma,

@@ -286,6 +286,10 @@ hipError_t launch_lattice_points(const LatticeArgs& L, long long ny, double* tx,
 // one another on the device, and its admission counts one batch of scratch.
 void set_setup_lanes(rbf_problem* p, int lanes);
 
+// ---- errors (capi.cpp) ---------------------------------------------------------
+// Sets the calling thread's rbf_last_error message and returns s.
+rbf_status set_error(rbf_status s, const char* fmt, ...);
+
 // ---- device block cache (capi.cpp) -------------------------------------------
 // Allocation from, and return to, the library's cache of device blocks (see
 // rbf_block_cache); *got is the size actually held.  cached_free takes a

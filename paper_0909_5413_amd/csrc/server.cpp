@@ -355,18 +355,18 @@ rbf_status rbf_server_create(const rbf_server_opts* opts, rbf_server** out) {
     rbf_server_default_opts(&o);
     if (opts) o = *opts;
     if (o.max_active < 1 || o.max_active > 64 || o.packed < 0 || o.packed > 8 ||
-        o.pack_max_points < 0) return RBF_EINVAL;
+        o.pack_max_points < 0)
+        return rbf::set_error(RBF_EINVAL, "server options: max_active in 1..64, packed in 0..8, "
+                                          "pack_max_points >= 0");
     rbf_server* s = new (std::nothrow) rbf_server();
-    if (!s) return RBF_ENOMEM;
+    if (!s) return rbf::set_error(RBF_ENOMEM, "server allocation");
     s->opts = o;
-    if (hipGetDevice(&s->device) != hipSuccess) {
-        delete s;
-        return RBF_EDEVICE;
-    }
+    hipError_t e = hipGetDevice(&s->device);
     size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    if (e == hipSuccess) e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) {
         delete s;
-        return RBF_EDEVICE;
+        return rbf::set_error(RBF_EDEVICE, "server device query: %s", hipGetErrorString(e));
     }
     s->budget = o.max_device_bytes ? o.max_device_bytes : (size_t)(0.9 * (double)free_b);
     s->workers_left = o.max_active;

@@ -406,3 +406,22 @@ def test_mixed_refinement_never_returns_a_worse_iterate(torch_dev, oracle_mod):
     slack = residual_gate(P, f, lam, 0.0)
     say("oracle residual", res, "reported", d["rel_residual"], "slack", slack)
     assert abs(res - d["rel_residual"]) <= slack
+
+
+def test_library_before_torch_load_order(torch_dev):
+    """A process that loads the library before it initialises PyTorch's device
+    still finds the GPU (the binding brings PyTorch's HIP runtime in first):
+    a small solve in a child process, in that order."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import paper_0909_5413_amd as R; from paper_0909_5413_amd import workloads as W; "
+            "R.lib(); import torch; torch.cuda.init(); w = W.MINI; p = w.points(); "
+            "h = R.rbf_setup(p, w.values(p), w.sigma, w.cutoff, 1); "
+            "lam, info, st = R.rbf_solve(h, w.n, R.default_opts(rtol=1e-10)); "
+            "s = R.rbf_server_create(); R.rbf_server_destroy(s); R.rbf_destroy(h); "
+            "print('ok', st, info.iterations)")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=180)
+    say("child", r.returncode, r.stdout.strip(), r.stderr.strip()[-300:])
+    assert r.returncode == 0 and r.stdout.startswith("ok 0"), r.stderr[-2000:]

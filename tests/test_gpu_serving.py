@@ -245,3 +245,70 @@ def test_stalled_mixed_requests_equal_alone(torch_dev):
                 assert np.array_equal(lam, lam0)
         finally:
             R.rbf_server_destroy(srv)
+
+
+def test_stall_stop_equal_alone(torch_dev):
+    """FP64 and FP64-with-FP32-inverse requests at h/sigma = 0.6, where
+    restarted GMRES stagnates, with the stall stop on (stall_cycles = 2): alone
+    each ends with RBF_ENOCONV after a few cycles, far below its iteration
+    budget, its residual above half of its value two cycles earlier; served by
+    the packed engines or one stream per request, each ends the same, bit for
+    bit.  With the stop off the same solve runs to its budget."""
+    reqs = W.serving_requests(3, seed_base=998000, n_lo=2e3, n_hi=8e3, hs_lo=0.6, hs_hi=0.62)
+    data = [(w, w.points()) for w in reqs]
+    ref = []
+    for i, (w, pts) in enumerate(data):
+        prec = (R.RBF_FP64, R.RBF_FP64_PC32)[i % 2]
+        opts = dict(rtol=1e-12, precision=prec, max_iters=3000, stall_cycles=2)
+        f = w.values(pts)
+        h = R.rbf_setup(pts, f, w.sigma, w.cutoff, w.overlap)
+        try:
+            lam, info, st = R.rbf_solve(h, w.n, R.default_opts(**opts),
+                                        ok=(R.RBF_OK, R.RBF_ENOCONV))
+            d = info.as_dict()
+            say("alone", w.name, w.n, R.status_name(st), d["iterations"], d["history"][-3:])
+            assert st == R.RBF_ENOCONV and d["iterations"] < 3000
+            hist = d["history"]
+            assert len(hist) >= 3 and hist[-1] > 0.5 * hist[-3]
+            assert "stalled" in R.last_error()
+            ref.append((lam, st, info.rel_residual, opts))
+            if i == 0:   # the stop off: the budget is spent
+                _, info2, st2 = R.rbf_solve(h, w.n, R.default_opts(
+                    rtol=1e-12, precision=prec, max_iters=150), ok=(R.RBF_OK, R.RBF_ENOCONV))
+                assert st2 == R.RBF_ENOCONV and info2.iterations == 150
+        finally:
+            R.rbf_destroy(h)
+    for packed in (2, 0):
+        srv = R.rbf_server_create(max_active=3, packed=packed)
+        try:
+            ids = [R.rbf_server_submit(srv, pts, w.values(pts), w.sigma, w.cutoff, w.overlap,
+                                       R.default_opts(**o)) for (w, pts), (_, _, _, o)
+                   in zip(data, ref)]
+            for (w, _), rid, (lam0, st0, rel0, _) in zip(data, ids, ref):
+                lam, res, st = R.rbf_server_wait(srv, rid, w.n)
+                say("served", packed, w.name, R.status_name(st), res.info.rel_residual)
+                assert st == st0
+                assert res.info.rel_residual == rel0
+                assert np.array_equal(lam, lam0)
+        finally:
+            R.rbf_server_destroy(srv)
+
+
+def test_stall_stop_leaves_converging_solves_alone(torch_dev):
+    """A system that converges (c0, h/sigma = 0.8, to 1e-12 over two cycles)
+    is not stopped by stall_cycles = 1, and its weights are bit-identical to
+    the solve with the stop off."""
+    w = W.C0
+    pts = w.points()
+    f = w.values(pts)
+    h = R.rbf_setup(pts, f, w.sigma, w.cutoff, w.overlap)
+    try:
+        lam0, i0, st0 = R.rbf_solve(h, w.n, R.default_opts(rtol=1e-12))
+        lam1, i1, st1 = R.rbf_solve(h, w.n, R.default_opts(rtol=1e-12, stall_cycles=1))
+        assert st0 == st1 == R.RBF_OK
+        assert i0.iterations == i1.iterations and np.array_equal(lam0, lam1)
+        with pytest.raises(R.RbfError) as e:
+            R.rbf_solve(h, w.n, R.default_opts(rtol=1e-12, stall_cycles=-1))
+        assert e.value.status == R.RBF_EINVAL
+    finally:
+        R.rbf_destroy(h)
