@@ -213,3 +213,14 @@ def test_box_truncated_noalloc_matches(torch_dev, problems):
     R.rbf_matvec_device_noalloc(h, dw, dy, R.RBF_FP64, torch_dev.cuda.current_stream())
     torch_dev.cuda.synchronize()
     assert np.array_equal(dy.cpu().numpy(), gpu_matvec(torch_dev, h, w))
+
+
+def test_box_truncated_product_is_deterministic(torch_dev, problems):
+    """The box-truncated product and its evaluation are bit-reproducible:
+    fixed summation orders, no atomics."""
+    h, P, pts, f, sigma, *_ = problems["vortex_big"]
+    w = W.random_weights(pts.shape[0], 77)
+    assert np.array_equal(gpu_matvec(torch_dev, h, w), gpu_matvec(torch_dev, h, w))
+    R.rbf_solve(h, pts.shape[0], R.default_opts(rtol=1e-8))
+    tg = off_grid_targets(pts, sigma, 78)
+    assert np.array_equal(R.rbf_evaluate(h, tg), R.rbf_evaluate(h, tg))

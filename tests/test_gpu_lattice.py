@@ -132,3 +132,9 @@ def test_lattice_box_truncated_equals_box_evaluation(torch_dev, oracle_mod):
                               R.rbf_evaluate(h, tg))
     finally:
         R.rbf_destroy(h)
+
+
+def test_lattice_is_deterministic(torch_dev, solved):
+    h, P, pts, lam, w = solved
+    args = lattices(w)["fine_wide"]
+    assert np.array_equal(R.rbf_evaluate_lattice(h, *args), R.rbf_evaluate_lattice(h, *args))
