@@ -78,7 +78,10 @@ __global__ __launch_bounds__(kBtThreads) void k_box_square(MatvecArgs a, BoxTrun
 // serves, for each group g of four targets, target 4 g + l / 16 with the
 // source phase p = 16 v + l % 16: the staged sources q = p, p + 64, ...  A
 // wave's 16 phases are summed by a butterfly, the waves' sums in wave order,
-// chunk after chunk.
+// chunk after chunk.  kCap: squares so wide that a pair's exponent can pass
+// the exponential's range, so d2 is capped (else no pair can, and the cap is
+// left out).
+template <bool kCap>
 __global__ __launch_bounds__(kBtThreads) void k_matvec64_box(MatvecArgs a, BoxTrunc bt,
                                                             const double* __restrict__ w,
                                                             double* __restrict__ y) {
@@ -123,7 +126,8 @@ __global__ __launch_bounds__(kBtThreads) void k_matvec64_box(MatvecArgs a, BoxTr
                 auto pair = [&](int q, double& acc) {
                     const double2 s = XY[q];
                     const double dx = xi - s.x, dy = yi - s.y;
-                    const double d2 = __builtin_fmin(__builtin_fma(dx, dx, dy * dy), d2max);
+                    double d2 = __builtin_fma(dx, dx, dy * dy);
+                    if (kCap) d2 = __builtin_fmin(d2, d2max);
                     acc = __builtin_fma(W[q], exp2_scaled_t32(d2, beta, T32), acc);
                 };
                 int q = ph;
@@ -201,7 +205,14 @@ hipError_t launch_box_square(const MatvecArgs& a, const BoxTrunc& bt, int* nsrc,
 
 hipError_t launch_matvec64_box(const MatvecArgs& a, const BoxTrunc& bt, const double* w,
                                double* y, hipStream_t st) {
-    if (bt.nbox > 0) k_matvec64_box<<<(unsigned)bt.nbox, kBtThreads, 0, st>>>(a, bt, w, y);
+    if (bt.nbox <= 0) return hipSuccess;
+    // a target lies within B/2 of its box's centre (up to rounding, taken
+    // here as 1%), a source within T/2, along each axis
+    const double reach = 1.01 * (0.5 * bt.bg.B + bt.halfT);
+    if (2.0 * reach * reach < bt.d2max)
+        k_matvec64_box<false><<<(unsigned)bt.nbox, kBtThreads, 0, st>>>(a, bt, w, y);
+    else
+        k_matvec64_box<true><<<(unsigned)bt.nbox, kBtThreads, 0, st>>>(a, bt, w, y);
     return hipGetLastError();
 }
 
