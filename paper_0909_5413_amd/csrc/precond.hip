@@ -754,11 +754,11 @@ __device__ __forceinline__ void stage_step(const T* __restrict__ A, const T* __r
 }
 
 // One step tile: rows R .. R + 16 kWS M - 1 of block column J.  The update
-// (MFMA, registers; the accumulators start from -A so that they end as the
-// negated updated tile, and the loads of A overlap the update), then the
-// panel solve x L_JJ^T = a split at the middle of L_JJ: x1 = a1 L11^-T by
-// substitution, a2 -= x1 L21^T on MFMA into the update's accumulators,
-// x2 = a2 L22^-T; both halves pass through LDS once.
+// (MFMA, registers: the accumulators sum L[row][k] L[col][k] over the finished
+// columns), then the tile a = A - sum, its matrix entries evaluated from the
+// staged coordinates, then the panel solve x L_JJ^T = a split at the middle of
+// L_JJ: x1 = a1 L11^-T by substitution, a2 -= x1 L21^T on MFMA into the
+// update's accumulators, x2 = a2 L22^-T; both halves pass through LDS once.
 template <typename T, int M>
 __device__ __forceinline__ void step_tile(T* __restrict__ A, const T* __restrict__ lt,
                                           const double2* __restrict__ xy, int np, int p,
@@ -1008,12 +1008,12 @@ __global__ __launch_bounds__(kT2, 2) void k_z_forward(PrecondArgs a, long long c
 }
 
 // Centre rows, back solve of block row I: L_II^T X_I = W_I - L[below, I]^T
-// X[below]; the slot's block rows are visited from its last one up.  One wave
-// per (slot, 64 right-hand sides): the product (32 rows x 64 columns, eight
-// 16x16 MFMA tiles) takes its operands straight from memory into registers,
-// each loaded once, the next chunk of 16 k in flight; W_I and the result move
-// through LDS with coalesced accesses, and the 32x32 triangular solve runs one
-// right-hand side per lane, unrolled in registers.
+// X[below]; the slot's block rows are visited from its last one up.  Two waves
+// per (slot, 64 right-hand sides): each forms the product for 32 of them (32
+// rows x 32 columns, four 16x16 MFMA tiles) with its operands straight from
+// memory into registers, the next chunk of 16 k in flight; W_I and the result
+// move through LDS with coalesced accesses, and wave 0 runs the 32x32
+// triangular solve, one right-hand side per lane, unrolled in registers.
 constexpr int kZT = 128;   // threads of the back-solve kernel (two waves)
 
 template <typename T>
