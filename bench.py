@@ -65,7 +65,8 @@ def step_kernel_flops(n_omega):
 
 def profiled_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current source of that kernel (else None)."""
+    summary, if it was taken on the current source of that kernel and of the
+    headers it includes (else None)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_traffic_c1.md")
@@ -76,8 +77,11 @@ def profiled_traffic(kernel):
         name, val, src, sha = m.groups()
         if name != kernel:
             continue
-        cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
-        return float(val) if cur == sha else None
+        # the kernel's source file and the headers it includes, hashed in order
+        h = hashlib.sha256()
+        for f in src.split(","):
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        return float(val) if h.hexdigest() == sha else None
     return None
 
 

@@ -126,7 +126,16 @@ __device__ __forceinline__ double exp2_scaled_t32(double d2, double beta, const 
     p = __builtin_fma(p, f, 0x1.ebfbdff7feebap-13);
     p = __builtin_fma(p, f, 0x1.62e42fefa39efp-6);
     p = __builtin_fma(p, f, 1.0);
-    return __builtin_amdgcn_ldexp(T[k & 31] * p, k >> 5);
+    // the byte offset 8 (k mod 32) of T[k mod 32] in one instruction: a shift
+    // by 3 whose result keeps only its low byte (SDWA destination select), where
+    // a mask and a shift would take two
+    unsigned off;
+    asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:BYTE_0 dst_unused:UNUSED_PAD src0_sel:DWORD "
+        "src1_sel:DWORD"
+        : "=v"(off)
+        : "v"(k));
+    const double tj = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(T) + off);
+    return __builtin_amdgcn_ldexp(tj * p, k >> 5);
 }
 
 // 2^x in FP32 on the hardware transcendental unit (v_exp_f32).
