@@ -71,10 +71,14 @@ def lattices(w):
         # coarser than the cells (cells without a column), uneven spacings
         "coarse": (-0.97, -1.02, 7.3 * w.sigma, 11.1 * w.sigma, 29, 19),
         "one_point": (0.1234, -0.4321, 1.0, 1.0, 1, 1),
+        # a single row and a single column crossing the grid and its border
+        "one_row": (-1.2, 0.0137, 0.6 * h, 1.0, 137, 1),
+        "one_col": (0.271, -1.15, 1.0, 0.8 * h, 1, 93),
     }
 
 
-@pytest.mark.parametrize("name", ["staggered", "fine_wide", "coarse", "one_point"])
+@pytest.mark.parametrize("name", ["staggered", "fine_wide", "coarse", "one_point", "one_row",
+                                  "one_col"])
 def test_lattice_matches_oracle(torch_dev, solved, name):
     h, P, pts, lam, w = solved
     x0, y0, hx, hy, nx, ny = lattices(w)[name]
